@@ -1,0 +1,204 @@
+/*
+ * rtsun.h -- C ABI of the MI355X library for refractive radio ray tracing
+ * through a gridded corona with step-wise ray-tube magnification and thermal
+ * free-free transfer.
+ *
+ * Paper: "Modeling the Thermal Low-Frequency Radio Sun with Ray Tracing".
+ * The calls follow its statement of the problem: a coronal grid of electron
+ * density and temperature (Sec. 3.1), frequencies in 40-800 MHz (Sec. 1) and
+ * an observer image plane (Sec. 3.2) go in; brightness-temperature maps
+ * (Sec. 3.3) and optionally the recorded ray paths with their geometric
+ * factors (Sec. 3.2, Figs. 4 and 6) come out.
+ *
+ * Units: lengths in solar radii (6.957e10 cm), n_e in cm^-3, T in K,
+ * frequencies in Hz, brightness temperatures in K.
+ *
+ * Conventions shared by every call:
+ *  - Status codes only; nothing throws across the ABI.  On failure the
+ *    thread-local message of rt_last_error_message() says why.
+ *  - Every argument and host-side value is validated before any device work.
+ *    RT_OK from a trace call means the work is enqueued on `hip_stream`
+ *    (a hipStream_t, NULL = the null stream); device faults surface at the next
+ *    call or at the caller's synchronisation as RT_E_DEVICE.
+ *  - Per-ray outcomes (exit, hit, miss, step limit) are data in rt_ray_info,
+ *    not errors.
+ *  - The caller owns every input and output buffer.  The library owns an
+ *    rt_model's device copy until rt_model_free, and its own scratch.
+ */
+#ifndef RTSUN_H
+#define RTSUN_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RT_ABI_VERSION 1u
+
+typedef enum {
+  RT_OK = 0,
+  RT_E_INVALID_ARG = 1,      /* bad pointer, size, descriptor field or version */
+  RT_E_NONFINITE_INPUT = 2,  /* NaN/Inf, n_e < 0 or T <= 0 in model values */
+  RT_E_OUT_OF_MEMORY = 3,    /* device allocation failed or RT_MAX_DEVICE_BYTES exceeded */
+  RT_E_DEVICE = 4,           /* no device, or a HIP runtime error */
+  RT_E_UNSUPPORTED = 5,      /* valid but not implemented combination */
+  RT_E_CAPACITY = 6,         /* a fixed-size limit of the library was exceeded */
+  RT_E_INTERNAL = 7
+} rt_status;
+
+/* Per-ray termination codes (rt_ray_info.code). */
+enum {
+  RT_RAY_EXIT_OUTER = 1,  /* left through the outer sphere r = r_max */
+  RT_RAY_HIT_INNER = 2,   /* reached the inner sphere r = r_in */
+  RT_RAY_MISS = 3,        /* impact parameter >= r_max: never entered */
+  RT_RAY_MAX_STEPS = 4,   /* step limit reached */
+  RT_RAY_NONFINITE = 5    /* state became NaN/Inf */
+};
+/* rt_ray_info.flags */
+enum { RT_RAY_FLAG_MARGINAL = 2 /* last-step fraction lambda within 1e-4 of 0 or 1 */ };
+
+/* ------------------------------------------------------------------------
+ * Model (Sec. 3.1: global corona on a spherical (r, theta, phi) grid).
+ * ------------------------------------------------------------------------ */
+typedef enum {
+  /* vertices r_a = r_in (r_max/r_in)^(a/(n0-1)), theta_b = (b+1/2) pi/n1,
+     phi_c = 2 pi c/n2 (periodic); n0, n1 >= 2, n2 >= 3 */
+  RT_GRID_SPHERICAL_LOGR = 0,
+  /* vertices origin[k] + i*spacing[k], edge-clamped; n0, n1, n2 >= 2 */
+  RT_GRID_CARTESIAN = 1
+} rt_grid_kind;
+
+typedef struct {
+  uint32_t abi_version;   /* RT_ABI_VERSION */
+  uint32_t kind;          /* rt_grid_kind */
+  int32_t n0, n1, n2;     /* (N_r, N_theta, N_phi) or (N_x, N_y, N_z) */
+  int32_t _reserved;
+  double r_in, r_max;     /* termination spheres; spherical grids span [r_in, r_max].
+                             For Cartesian grids r_in <= 0 disables the inner sphere. */
+  double origin[3];       /* Cartesian only */
+  double spacing[3];      /* Cartesian only, > 0 */
+} rt_grid_desc;
+
+typedef struct rt_model rt_model;  /* opaque: device-resident packed model */
+
+/* Load a model.  ne, te: HOST arrays, float32, C-order [n0][n1][n2], read
+ * before the call returns.  Values must be finite, ne >= 0, te > 0.
+ * The packed device copy (n_e, index-space vertex gradient, T) is built on
+ * `device`, ordered on `hip_stream`; the call synchronises that stream.
+ * On success *out owns the device memory until rt_model_free. */
+rt_status rt_model_load(const rt_grid_desc* desc, const float* ne, const float* te, int32_t device,
+                        void* hip_stream, rt_model** out);
+
+/* Replace a model's values (same shape).  on_device = 0: host pointers,
+ * validated on the host; on_device = 1: device pointers on the model's device,
+ * validated by a device reduction (this synchronises `hip_stream`).  Must not
+ * race a trace that reads the same model. */
+rt_status rt_model_update(rt_model* model, const float* ne, const float* te, int32_t on_device,
+                          void* hip_stream);
+
+/* Free a model (NULL is a no-op).  Synchronises the device first. */
+void rt_model_free(rt_model* model);
+
+/* ------------------------------------------------------------------------
+ * Observer image plane (Sec. 3.2): parallel rays launched from the observer.
+ * o = obs_dir / |obs_dir| (Sun -> observer), u = up x o (normalised), v = o x u.
+ * Pixel (j, i), j along u, i along v, has centre (-half_u + (j+1/2) 2 half_u/nu,
+ * -half_v + (i+1/2) 2 half_v/nv).  The ray starts on the r_max sphere and
+ * travels along -o; impact parameter >= r_max gives RT_RAY_MISS.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+  double obs_dir[3];
+  double up[3];
+  int32_t nu, nv;
+  double half_u, half_v;
+} rt_image_desc;
+
+/* rt_params.flags */
+enum {
+  RT_USE_MAGNIFICATION = 1u << 0,  /* geometric d ln S/ds term (Eqs. 2-3, 7-12) */
+  RT_USE_REFRACTION = 1u << 1,     /* off: straight lines of sight, n taken as 1 (Sec. 3.3) */
+  RT_PREC_ALL_FP32 = 1u << 2,      /* area estimate and transfer in FP32 instead of FP64 */
+  RT_SCHED_PLAIN = 1u << 3,        /* one launch per (model, frequency) image instead of
+                                      one persistent launch over all of them */
+  RT_DETERMINISTIC_GRAD = 1u << 4, /* reserved */
+  RT_TEST_NO_ABSORPTION = 1u << 30 /* kappa = 0 (tests of I*S = const, Eq. 1) */
+};
+
+typedef struct {
+  uint32_t abi_version;     /* RT_ABI_VERSION */
+  uint32_t flags;
+  double ds_max;            /* step rule dt = ds_max / max(n(r_i), n_floor) (arc length <= ds_max) */
+  double n_floor;           /* in (0, 1]; 1 gives the fixed dt = ds_max of Sec. 2.1 */
+  int32_t max_steps;        /* >= 1 */
+  int32_t checkpoint_every; /* adjoint: ray-state checkpoint interval K (>= 1) */
+  double perturb_ratio;     /* eta of Eq. 8, > 0 */
+  double tb_inner_K;        /* boundary brightness behind a ray that reaches r_in */
+  double tb_sky_K;          /* boundary brightness behind a ray that leaves (or misses) */
+} rt_params;
+
+/* Fill *p with defaults: magnification + refraction, ds_max 0.005, n_floor 1,
+ * max_steps 200000, checkpoint_every 64, eta 1e-2, tb_inner 1e4 K, tb_sky 0. */
+void rt_params_default(rt_params* p);
+
+typedef struct {
+  int32_t n_steps;      /* central steps taken, the truncated last one included */
+  int8_t code;          /* RT_RAY_* */
+  int8_t flags;         /* RT_RAY_FLAG_* */
+  int8_t _pad[2];
+  float exit_pos[3];    /* end point (on the crossed sphere for EXIT/HIT) */
+  float tau;            /* total optical depth */
+  float ln_s_end;       /* ln(S_end / S_0) = sum lambda_i ln M_i (Fig. 6) */
+  float r_min;          /* smallest |r| among step points */
+} rt_ray_info;          /* 32 bytes */
+
+typedef struct {
+  unsigned long long ray_steps;   /* sum of n_steps over all rays of the call */
+  unsigned int max_steps;         /* largest n_steps */
+  unsigned int code_count[6];     /* rays per code (index = code) */
+  unsigned int _pad;
+} rt_trace_stats;                 /* 40 bytes */
+
+/* Trace maps for every (model, frequency) pair.
+ *  models[n_models]: all on the current device, sharing one grid kind.
+ *  freq_hz[n_freq]: HOST array, each > 0.
+ *  tb_out: DEVICE float32 [n_models][n_freq][nv][nu] (required).
+ *  info_out: DEVICE rt_ray_info with the same shape, or NULL.
+ *  stats_out: DEVICE rt_trace_stats, or NULL; overwritten.
+ *  Paths (optional, all NULL/0 to disable): path_rays = HOST sorted, distinct
+ *  flat ray indices into the tb_out shape; path_out = DEVICE float32
+ *  [n_path_rays][path_capacity][9] records (x, y, z, s, ln M, d ln S/ds,
+ *  tau, n_e, T) per step after the step; path_len_out = DEVICE int32
+ *  [n_path_rays] (steps recorded, <= path_capacity; longer paths are
+ *  truncated and the ray's flags are unaffected).
+ * RT_SCHED_PLAIN selects one launch per image; otherwise one persistent launch
+ * covers all rays and refills lanes whose ray has finished.  Both give
+ * bitwise-identical results. */
+rt_status rt_trace_maps(const rt_model* const* models, int32_t n_models, const double* freq_hz,
+                        int32_t n_freq, const rt_image_desc* image, const rt_params* params,
+                        float* tb_out, rt_ray_info* info_out, rt_trace_stats* stats_out,
+                        const int32_t* path_rays, int32_t n_path_rays, int32_t path_capacity,
+                        float* path_out, int32_t* path_len_out, void* hip_stream);
+
+/* Reverse-mode gradient of L = sum_{f,i,j} w[f][i][j] T_b[f][i][j] with
+ * respect to ln n_e and ln T at every grid vertex, for one model.
+ *  weights: DEVICE float32 [n_freq][nv][nu]; loss_out: DEVICE double scalar;
+ *  grad_ln_ne, grad_ln_te: DEVICE float32 [n0][n1][n2], overwritten;
+ *  tb_out: DEVICE float32 [n_freq][nv][nu] or NULL.
+ * Ray states are checkpointed every params->checkpoint_every steps and
+ * recomputed in reverse; gradients are scattered with float atomics, so
+ * their summation order (and last bits) can vary between runs. */
+rt_status rt_trace_adjoint(const rt_model* model, const double* freq_hz, int32_t n_freq,
+                           const rt_image_desc* image, const rt_params* params, const float* weights,
+                           double* loss_out, float* grad_ln_ne, float* grad_ln_te, float* tb_out,
+                           void* hip_stream);
+
+const char* rt_status_string(rt_status s);
+const char* rt_last_error_message(void);
+uint32_t rt_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RTSUN_H */

@@ -18,7 +18,7 @@ SRC_PATH = os.path.join(_HERE, "rt_oracle.cpp")
 
 # Per-ray termination codes and flags (same numbering as the GPU library's ABI).
 EXIT_OUTER, HIT_INNER, MISS, MAX_STEPS, NONFINITE = 1, 2, 3, 4, 5
-GRAZING, MARGINAL = 1, 2
+GRAZING, MARGINAL, POLAR = 1, 2, 4
 
 GRID_SPHERICAL_LOGR, GRID_CARTESIAN = 0, 1
 ANALYTIC_BA, ANALYTIC_UNIFORM, ANALYTIC_SLAB, ANALYTIC_LENS = 10, 11, 12, 13

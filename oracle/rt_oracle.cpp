@@ -45,7 +45,7 @@ constexpr double kFpCoef = 8.98e3;     // f_p [Hz] = 8.98e3 sqrt(n_e [cm^-3])
 constexpr double kFFCoef = 9.78e-3;    // free-free absorption constant (Dulk 1985)
 
 enum Code : int32_t { RUNNING = 0, EXIT_OUTER = 1, HIT_INNER = 2, MISS = 3, MAX_STEPS = 4, NONFINITE = 5 };
-enum Flag : int32_t { GRAZING = 1, MARGINAL = 2 };
+enum Flag : int32_t { GRAZING = 1, MARGINAL = 2, POLAR = 4 };
 
 enum MediumKind : int32_t {
   GRID_SPHERICAL_LOGR = 0, GRID_CARTESIAN = 1,
@@ -209,7 +209,7 @@ Sample<S> eval_medium(const Medium& m, const Src& src, const V3<S>& pos, bool wa
       // The density gradient that drives the rays is the trilinear interpolant of
       // per-vertex central differences in index space (one-sided at the r and theta
       // edges, periodic in phi), mapped to Cartesian with the spherical unit
-      // vectors; it is continuous across cell faces.
+      // vectors; it is continuous across cell faces and across the clamped edges.
       const int nr = m.n0, nt = m.n1, np = m.n2;
       const double dl = std::log(m.r_max / m.r_in) / double(nr - 1);
       const double dth = kPi / double(nt);
@@ -258,8 +258,10 @@ Sample<S> eval_medium(const Medium& m, const Src& src, const V3<S>& pos, bool wa
       trilinear(gr, u, v, w, dnu, d1, d2, d3);
       trilinear(gt, u, v, w, dnv, d1, d2, d3);
       trilinear(gp, u, v, w, dnw, d1, d2, d3);
-      if (cr) dnu = S(0.0);
-      if (ct) dnv = S(0.0);
+      // Beyond an edge the index is clamped: the value is held and the gradient
+      // is the edge vertex's, so the force stays continuous across r_in, r_max
+      // and the polar rows (a ray starts on the r_max sphere).
+      (void)cr; (void)ct;
       // Chain rule to Cartesian with the spherical unit vectors.
       S st = rho / r, ctv = pos.z / r;
       V3<S> rhat = (S(1.0) / r) * pos;
@@ -311,10 +313,8 @@ Sample<S> eval_medium(const Medium& m, const Src& src, const V3<S>& pos, bool wa
       trilinear(f, fr[0], fr[1], fr[2], out.ne, d0, d1, d2);
       if (want_te) trilinear(g, fr[0], fr[1], fr[2], out.te, d0, d1, d2);
       S gi[3];
-      for (int ax = 0; ax < 3; ++ax) {
-        trilinear(gx[ax], fr[0], fr[1], fr[2], gi[ax], d0, d1, d2);
-        if (cl[ax]) gi[ax] = S(0.0);
-      }
+      for (int ax = 0; ax < 3; ++ax) trilinear(gx[ax], fr[0], fr[1], fr[2], gi[ax], d0, d1, d2);
+      (void)cl;
       out.grad = {gi[0] / S(m.spacing[0]), gi[1] / S(m.spacing[1]), gi[2] / S(m.spacing[2])};
       break;
     }
@@ -446,6 +446,12 @@ RayOut<S> trace_rk4(const Medium& m, const Src& src, const Params& P, double f,
   double rmin = vnorm(r), lam_last = 1.0;
   V3<double> exitp{val(r.x), val(r.y), val(r.z)};
   S tau(0.0), lns(0.0), s_arc(0.0);
+  // smallest angular distance of a step point from the polar axis
+  auto axis_angle = [](const V3<S>& x) {
+    double rho = std::sqrt(val(x.x) * val(x.x) + val(x.y) * val(x.y));
+    return std::atan2(rho, std::fabs(val(x.z)));
+  };
+  double min_axis = axis_angle(r);
   const bool inner = m.r_in > 0.0;
   for (int i = 0; i < P.max_steps; ++i) {
     // Step size: dt = ds_max / max(n(r_i), n_floor); arc length n dt <= ds_max.
@@ -526,6 +532,7 @@ RayOut<S> trace_rk4(const Medium& m, const Src& src, const Params& P, double f,
     r = r1;
     p = p1;
     rmin = std::min(rmin, vnorm(r));
+    min_axis = std::min(min_axis, axis_angle(r));
     if (L0 > 0.0) bdrift = std::max(bdrift, std::fabs(vnorm(cross(r, p)) - L0) / L0);
     if (refr) {
       Sample<S> sh = eval_medium(m, src, r, false);
@@ -549,6 +556,10 @@ RayOut<S> trace_rk4(const Medium& m, const Src& src, const Params& P, double f,
   out.ham_drift = hdrift;
   if ((code == EXIT_OUTER || code == HIT_INNER) && (lam_last < 1e-4 || lam_last > 1.0 - 1e-4))
     out.flags |= MARGINAL;
+  // Near the polar axis of a spherical grid the theta rows are clamped and the
+  // azimuthal derivative is divided by rho -> 0: the force is singular there and
+  // a ray passing through it is ill-conditioned.
+  if (m.kind == GRID_SPHERICAL_LOGR && min_axis < 2.0 * (0.5 * kPi / double(m.n1))) out.flags |= POLAR;
   return out;
 }
 

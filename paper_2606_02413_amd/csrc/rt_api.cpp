@@ -1,0 +1,492 @@
+// C ABI: argument and value validation on the host, model staging, and the
+// launch plan of a trace call.  All device work is ordered on the caller's
+// stream.
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "rt_internal.hpp"
+
+using namespace rt;
+
+namespace {
+
+thread_local std::string g_err;
+
+rt_status fail(rt_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+std::atomic<long long> g_device_bytes{0};
+
+long long byte_cap() {
+  const char* e = std::getenv("RT_MAX_DEVICE_BYTES");
+  if (!e || !*e) return -1;
+  char* end = nullptr;
+  long long v = std::strtoll(e, &end, 10);
+  return (end && *end == '\0' && v >= 0) ? v : -1;
+}
+
+// Allocation through one place so the optional byte cap applies everywhere.
+rt_status dev_alloc(void** p, size_t bytes, const char* what) {
+  const long long cap = byte_cap();
+  if (cap >= 0 && g_device_bytes.load() + (long long)bytes > cap)
+    return fail(RT_E_OUT_OF_MEMORY, std::string(what) + ": RT_MAX_DEVICE_BYTES exceeded");
+  hipError_t e = hipMalloc(p, bytes);
+  if (e == hipErrorOutOfMemory) return fail(RT_E_OUT_OF_MEMORY, std::string(what) + ": hipMalloc out of memory");
+  if (e != hipSuccess) return fail(RT_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+  g_device_bytes += (long long)bytes;
+  return RT_OK;
+}
+
+void dev_free(void* p, size_t bytes) {
+  if (!p) return;
+  (void)hipFree(p);
+  g_device_bytes -= (long long)bytes;
+}
+
+rt_status hip_check(hipError_t e, const char* what) {
+  if (e == hipSuccess) return RT_OK;
+  return fail(RT_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+bool finite3(const double* v) { return std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]); }
+
+// Per-device scratch owned by the library: claim counters of persistent launches
+// (a ring of slots, so consecutive calls do not share counters) and the device
+// copy of a call's path-ray list.
+struct DeviceScratch {
+  unsigned* counters = nullptr;
+  unsigned next_slot = 0;
+  int32_t* path_rays = nullptr;
+  size_t path_cap = 0;
+  int n_cu = 0;
+};
+constexpr unsigned kCounterSlots = 1024;
+std::mutex g_scratch_mu;
+DeviceScratch g_scratch[64];
+
+rt_status scratch_for(int dev, DeviceScratch** out) {
+  if (dev < 0 || dev >= 64) return fail(RT_E_DEVICE, "device index out of range");
+  DeviceScratch& s = g_scratch[dev];
+  if (!s.counters) {
+    void* p = nullptr;
+    rt_status st = dev_alloc(&p, sizeof(unsigned) * kXcds * kCounterSlots, "work-queue counters");
+    if (st != RT_OK) return st;
+    s.counters = static_cast<unsigned*>(p);
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n < 1) n = 1;
+    s.n_cu = n;
+  }
+  *out = &s;
+  return RT_OK;
+}
+
+}  // namespace
+
+struct rt_model {
+  rt_grid_desc desc;
+  DevGeom geom;
+  int device;
+  float4* nfg;
+  float* te;
+  size_t nfg_bytes, te_bytes;
+  float* raw_ne;  // staging copies of the input arrays (C-order)
+  float* raw_te;
+  size_t raw_bytes;
+};
+
+namespace {
+
+rt_status validate_desc(const rt_grid_desc* d) {
+  if (!d) return fail(RT_E_INVALID_ARG, "desc is NULL");
+  if (d->abi_version != RT_ABI_VERSION) return fail(RT_E_INVALID_ARG, "desc->abi_version mismatch");
+  if (d->kind == RT_GRID_SPHERICAL_LOGR) {
+    if (d->n0 < 2 || d->n1 < 2 || d->n2 < 3) return fail(RT_E_INVALID_ARG, "spherical grid needs n0, n1 >= 2, n2 >= 3");
+    if (!(std::isfinite(d->r_in) && std::isfinite(d->r_max) && d->r_in > 0.0 && d->r_max > d->r_in))
+      return fail(RT_E_INVALID_ARG, "spherical grid needs 0 < r_in < r_max");
+  } else if (d->kind == RT_GRID_CARTESIAN) {
+    if (d->n0 < 2 || d->n1 < 2 || d->n2 < 2) return fail(RT_E_INVALID_ARG, "Cartesian grid needs n >= 2 per axis");
+    if (!finite3(d->origin) || !finite3(d->spacing)) return fail(RT_E_INVALID_ARG, "origin/spacing not finite");
+    for (int k = 0; k < 3; ++k)
+      if (!(d->spacing[k] > 0.0)) return fail(RT_E_INVALID_ARG, "spacing must be > 0");
+    if (!(std::isfinite(d->r_in) && std::isfinite(d->r_max) && d->r_max > 0.0 && d->r_in < d->r_max))
+      return fail(RT_E_INVALID_ARG, "need r_in < r_max, r_max > 0");
+  } else {
+    return fail(RT_E_INVALID_ARG, "unknown grid kind");
+  }
+  const long long n = (long long)d->n0 * d->n1 * d->n2;
+  if (n > (1ll << 31) - 1) return fail(RT_E_CAPACITY, "grid has more than 2^31-1 vertices");
+  return RT_OK;
+}
+
+rt_status validate_values_host(const float* ne, const float* te, long long n) {
+  for (long long i = 0; i < n; ++i) {
+    const float x = ne[i], t = te[i];
+    if (!(std::isfinite(x) && x >= 0.0f)) return fail(RT_E_NONFINITE_INPUT, "n_e[" + std::to_string(i) + "] is not finite and >= 0");
+    if (!(std::isfinite(t) && t > 0.0f)) return fail(RT_E_NONFINITE_INPUT, "T[" + std::to_string(i) + "] is not finite and > 0");
+  }
+  return RT_OK;
+}
+
+DevGeom make_geom(const rt_grid_desc& d) {
+  DevGeom g{};
+  g.kind = int(d.kind);
+  g.n0 = d.n0; g.n1 = d.n1; g.n2 = d.n2;
+  g.n2p = (d.kind == RT_GRID_SPHERICAL_LOGR) ? d.n2 + 1 : d.n2;
+  if (d.kind == RT_GRID_SPHERICAL_LOGR) {
+    const double dl = std::log(d.r_max / d.r_in) / double(d.n0 - 1);
+    g.ln_rin_d = std::log(d.r_in);
+    g.inv_dl_d = 1.0 / dl;
+    g.inv_dth_d = double(d.n1) / M_PI;
+    g.inv_dph_d = double(d.n2) / (2.0 * M_PI);
+    g.ln_rin = float(g.ln_rin_d);
+    g.inv_dl = float(g.inv_dl_d);
+    g.inv_dth = float(g.inv_dth_d);
+    g.inv_dph = float(g.inv_dph_d);
+    g.has_inner = 1;
+  } else {
+    for (int k = 0; k < 3; ++k) {
+      g.org_d[k] = d.origin[k];
+      g.inv_sp_d[k] = 1.0 / d.spacing[k];
+      g.org[k] = float(g.org_d[k]);
+      g.inv_sp[k] = float(g.inv_sp_d[k]);
+    }
+    g.has_inner = d.r_in > 0.0 ? 1 : 0;
+  }
+  g.r_in = d.r_in;
+  g.r_max = d.r_max;
+  return g;
+}
+
+bool same_grid(const rt_grid_desc& a, const rt_grid_desc& b) {
+  if (a.kind != b.kind || a.n0 != b.n0 || a.n1 != b.n1 || a.n2 != b.n2 || a.r_in != b.r_in || a.r_max != b.r_max)
+    return false;
+  if (a.kind == RT_GRID_CARTESIAN)
+    for (int k = 0; k < 3; ++k)
+      if (a.origin[k] != b.origin[k] || a.spacing[k] != b.spacing[k]) return false;
+  return true;
+}
+
+rt_status stage_model(rt_model* m, hipStream_t s) {
+  hipError_t e = launch_pack(m->geom, m->raw_ne, m->raw_te, m->nfg, m->te, s);
+  if (e != hipSuccess) return hip_check(e, "pack kernel");
+  return hip_check(hipStreamSynchronize(s), "model staging");
+}
+
+void free_model_memory(rt_model* m) {
+  dev_free(m->nfg, m->nfg_bytes);
+  dev_free(m->te, m->te_bytes);
+  dev_free(m->raw_ne, m->raw_bytes);
+  dev_free(m->raw_te, m->raw_bytes);
+  m->nfg = nullptr; m->te = nullptr; m->raw_ne = nullptr; m->raw_te = nullptr;
+}
+
+}  // namespace
+
+extern "C" {
+
+uint32_t rt_abi_version(void) { return RT_ABI_VERSION; }
+
+const char* rt_status_string(rt_status s) {
+  switch (s) {
+    case RT_OK: return "RT_OK";
+    case RT_E_INVALID_ARG: return "RT_E_INVALID_ARG";
+    case RT_E_NONFINITE_INPUT: return "RT_E_NONFINITE_INPUT";
+    case RT_E_OUT_OF_MEMORY: return "RT_E_OUT_OF_MEMORY";
+    case RT_E_DEVICE: return "RT_E_DEVICE";
+    case RT_E_UNSUPPORTED: return "RT_E_UNSUPPORTED";
+    case RT_E_CAPACITY: return "RT_E_CAPACITY";
+    case RT_E_INTERNAL: return "RT_E_INTERNAL";
+  }
+  return "unknown rt_status";
+}
+
+const char* rt_last_error_message(void) { return g_err.c_str(); }
+
+void rt_params_default(rt_params* p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof(*p));
+  p->abi_version = RT_ABI_VERSION;
+  p->flags = RT_USE_MAGNIFICATION | RT_USE_REFRACTION;
+  p->ds_max = 0.005;
+  p->n_floor = 1.0;
+  p->max_steps = 200000;
+  p->checkpoint_every = 64;
+  p->perturb_ratio = 1e-2;
+  p->tb_inner_K = 1.0e4;
+  p->tb_sky_K = 0.0;
+}
+
+rt_status rt_model_load(const rt_grid_desc* desc, const float* ne, const float* te, int32_t device, void* hip_stream,
+                        rt_model** out) {
+  try {
+    if (!out) return fail(RT_E_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    rt_status st = validate_desc(desc);
+    if (st != RT_OK) return st;
+    if (!ne || !te) return fail(RT_E_INVALID_ARG, "ne/te is NULL");
+    const long long n = (long long)desc->n0 * desc->n1 * desc->n2;
+    st = validate_values_host(ne, te, n);
+    if (st != RT_OK) return st;
+    rt_model* m = new (std::nothrow) rt_model();
+    if (!m) return fail(RT_E_OUT_OF_MEMORY, "host allocation");
+    m->desc = *desc;
+    m->geom = make_geom(*desc);
+    m->device = device;
+    const long long np = (long long)desc->n0 * desc->n1 * m->geom.n2p;
+    m->nfg_bytes = size_t(np) * sizeof(float4);
+    m->te_bytes = size_t(np) * sizeof(float);
+    m->raw_bytes = size_t(n) * sizeof(float);
+    const long long cap = byte_cap();
+    if (cap >= 0 && g_device_bytes.load() + (long long)(m->nfg_bytes + m->te_bytes + 2 * m->raw_bytes) > cap) {
+      delete m;
+      return fail(RT_E_OUT_OF_MEMORY, "model: RT_MAX_DEVICE_BYTES exceeded");
+    }
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
+      delete m;
+      return fail(RT_E_DEVICE, "no HIP device");
+    }
+    if (device < 0 || device >= ndev) {
+      delete m;
+      return fail(RT_E_INVALID_ARG, "device index out of range");
+    }
+    st = hip_check(hipSetDevice(device), "hipSetDevice");
+    if (st == RT_OK) st = dev_alloc((void**)&m->nfg, m->nfg_bytes, "model nfg");
+    if (st == RT_OK) st = dev_alloc((void**)&m->te, m->te_bytes, "model T");
+    if (st == RT_OK) st = dev_alloc((void**)&m->raw_ne, m->raw_bytes, "model staging n_e");
+    if (st == RT_OK) st = dev_alloc((void**)&m->raw_te, m->raw_bytes, "model staging T");
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    if (st == RT_OK) st = hip_check(hipMemcpyAsync(m->raw_ne, ne, m->raw_bytes, hipMemcpyHostToDevice, s), "copy n_e");
+    if (st == RT_OK) st = hip_check(hipMemcpyAsync(m->raw_te, te, m->raw_bytes, hipMemcpyHostToDevice, s), "copy T");
+    if (st == RT_OK) st = stage_model(m, s);
+    if (st != RT_OK) {
+      free_model_memory(m);
+      delete m;
+      return st;
+    }
+    *out = m;
+    return RT_OK;
+  } catch (...) {
+    return fail(RT_E_INTERNAL, "unexpected exception");
+  }
+}
+
+rt_status rt_model_update(rt_model* m, const float* ne, const float* te, int32_t on_device, void* hip_stream) {
+  try {
+    if (!m) return fail(RT_E_INVALID_ARG, "model is NULL");
+    if (!ne || !te) return fail(RT_E_INVALID_ARG, "ne/te is NULL");
+    if (on_device != 0 && on_device != 1) return fail(RT_E_INVALID_ARG, "on_device must be 0 or 1");
+    const long long n = (long long)m->desc.n0 * m->desc.n1 * m->desc.n2;
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    rt_status st = hip_check(hipSetDevice(m->device), "hipSetDevice");
+    if (st != RT_OK) return st;
+    if (on_device == 0) {
+      st = validate_values_host(ne, te, n);
+      if (st != RT_OK) return st;
+      st = hip_check(hipMemcpyAsync(m->raw_ne, ne, m->raw_bytes, hipMemcpyHostToDevice, s), "copy n_e");
+      if (st == RT_OK) st = hip_check(hipMemcpyAsync(m->raw_te, te, m->raw_bytes, hipMemcpyHostToDevice, s), "copy T");
+      if (st != RT_OK) return st;
+    } else {
+      // Device inputs: count invalid values with a reduction, then copy.
+      int* bad = nullptr;
+      st = dev_alloc((void**)&bad, sizeof(int), "validation counter");
+      if (st != RT_OK) return st;
+      int hbad = 0;
+      st = hip_check(launch_fill_u32(reinterpret_cast<unsigned*>(bad), 0u, 1, s), "fill");
+      if (st == RT_OK) st = hip_check(launch_validate(ne, te, n, bad, s), "validate kernel");
+      if (st == RT_OK) st = hip_check(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, s), "copy count");
+      if (st == RT_OK) st = hip_check(hipStreamSynchronize(s), "validate sync");
+      dev_free(bad, sizeof(int));
+      if (st != RT_OK) return st;
+      if (hbad != 0)
+        return fail(RT_E_NONFINITE_INPUT, std::to_string(hbad) + " model values are not finite or out of range");
+      st = hip_check(hipMemcpyAsync(m->raw_ne, ne, m->raw_bytes, hipMemcpyDeviceToDevice, s), "copy n_e");
+      if (st == RT_OK) st = hip_check(hipMemcpyAsync(m->raw_te, te, m->raw_bytes, hipMemcpyDeviceToDevice, s), "copy T");
+      if (st != RT_OK) return st;
+    }
+    return stage_model(m, s);
+  } catch (...) {
+    return fail(RT_E_INTERNAL, "unexpected exception");
+  }
+}
+
+void rt_model_free(rt_model* m) {
+  if (!m) return;
+  if (hipSetDevice(m->device) == hipSuccess) (void)hipDeviceSynchronize();
+  free_model_memory(m);
+  delete m;
+}
+
+rt_status rt_trace_maps(const rt_model* const* models, int32_t n_models, const double* freq_hz, int32_t n_freq,
+                        const rt_image_desc* image, const rt_params* params, float* tb_out, rt_ray_info* info_out,
+                        rt_trace_stats* stats_out, const int32_t* path_rays, int32_t n_path_rays,
+                        int32_t path_capacity, float* path_out, int32_t* path_len_out, void* hip_stream) {
+  try {
+    // ---- validation (host only) ----
+    if (!models || n_models < 1) return fail(RT_E_INVALID_ARG, "need at least one model");
+    if (!freq_hz || n_freq < 1) return fail(RT_E_INVALID_ARG, "need at least one frequency");
+    if (!image || !params || !tb_out) return fail(RT_E_INVALID_ARG, "image/params/tb_out is NULL");
+    for (int k = 0; k < n_models; ++k)
+      if (!models[k]) return fail(RT_E_INVALID_ARG, "models[" + std::to_string(k) + "] is NULL");
+    const rt_model* m0 = models[0];
+    for (int k = 1; k < n_models; ++k) {
+      if (!same_grid(models[k]->desc, m0->desc)) return fail(RT_E_INVALID_ARG, "models must share one grid descriptor");
+      if (models[k]->device != m0->device) return fail(RT_E_INVALID_ARG, "models must be on one device");
+    }
+    for (int k = 0; k < n_freq; ++k)
+      if (!(std::isfinite(freq_hz[k]) && freq_hz[k] > 0.0)) return fail(RT_E_INVALID_ARG, "frequencies must be finite and > 0");
+    if (n_models > kMaxModels) return fail(RT_E_CAPACITY, "more than 16 models in one call");
+    if (n_freq > kMaxFreqs) return fail(RT_E_CAPACITY, "more than 128 frequencies in one call");
+    const rt_params& P = *params;
+    if (P.abi_version != RT_ABI_VERSION) return fail(RT_E_INVALID_ARG, "params->abi_version mismatch");
+    const uint32_t known = RT_USE_MAGNIFICATION | RT_USE_REFRACTION | RT_PREC_ALL_FP32 | RT_SCHED_PLAIN |
+                           RT_DETERMINISTIC_GRAD | RT_TEST_NO_ABSORPTION;
+    if (P.flags & ~known) return fail(RT_E_INVALID_ARG, "unknown flag bits");
+    if (!(std::isfinite(P.ds_max) && P.ds_max > 0.0)) return fail(RT_E_INVALID_ARG, "ds_max must be > 0");
+    if (!(std::isfinite(P.n_floor) && P.n_floor > 0.0 && P.n_floor <= 1.0)) return fail(RT_E_INVALID_ARG, "n_floor must be in (0, 1]");
+    if (P.max_steps < 1) return fail(RT_E_INVALID_ARG, "max_steps must be >= 1");
+    if (!(std::isfinite(P.perturb_ratio) && P.perturb_ratio > 0.0)) return fail(RT_E_INVALID_ARG, "perturb_ratio must be > 0");
+    if (!(std::isfinite(P.tb_inner_K) && std::isfinite(P.tb_sky_K))) return fail(RT_E_INVALID_ARG, "boundary temperatures must be finite");
+    const rt_image_desc& I = *image;
+    if (I.nu < 1 || I.nv < 1) return fail(RT_E_INVALID_ARG, "image needs nu, nv >= 1");
+    if (!(std::isfinite(I.half_u) && std::isfinite(I.half_v) && I.half_u > 0 && I.half_v > 0))
+      return fail(RT_E_INVALID_ARG, "image half widths must be > 0");
+    if (!finite3(I.obs_dir) || !finite3(I.up)) return fail(RT_E_INVALID_ARG, "obs_dir/up not finite");
+    double o[3] = {I.obs_dir[0], I.obs_dir[1], I.obs_dir[2]};
+    const double on = std::sqrt(o[0] * o[0] + o[1] * o[1] + o[2] * o[2]);
+    if (!(on > 0)) return fail(RT_E_INVALID_ARG, "obs_dir is zero");
+    for (double& x : o) x /= on;
+    double u[3] = {I.up[1] * o[2] - I.up[2] * o[1], I.up[2] * o[0] - I.up[0] * o[2], I.up[0] * o[1] - I.up[1] * o[0]};
+    const double un = std::sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+    if (!(un > 1e-12)) return fail(RT_E_INVALID_ARG, "up is parallel to obs_dir");
+    for (double& x : u) x /= un;
+    const double v[3] = {o[1] * u[2] - o[2] * u[1], o[2] * u[0] - o[0] * u[2], o[0] * u[1] - o[1] * u[0]};
+    const long long npx = (long long)I.nu * I.nv;
+    const long long total = npx * n_models * n_freq;
+    if (total > (1ll << 31) - 1) return fail(RT_E_CAPACITY, "more than 2^31-1 rays in one call");
+    if (n_path_rays < 0) return fail(RT_E_INVALID_ARG, "n_path_rays < 0");
+    if (n_path_rays > 0) {
+      if (!path_rays || !path_out || !path_len_out || path_capacity < 1)
+        return fail(RT_E_INVALID_ARG, "path outputs need path_rays, path_out, path_len_out and capacity >= 1");
+      for (int k = 0; k < n_path_rays; ++k) {
+        if (path_rays[k] < 0 || path_rays[k] >= total) return fail(RT_E_INVALID_ARG, "path ray index out of range");
+        if (k > 0 && path_rays[k] <= path_rays[k - 1]) return fail(RT_E_INVALID_ARG, "path rays must be sorted and distinct");
+      }
+    }
+
+    // ---- launch plan ----
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    rt_status st = hip_check(hipSetDevice(m0->device), "hipSetDevice");
+    if (st != RT_OK) return st;
+    DeviceScratch* sc = nullptr;
+    {
+      std::lock_guard<std::mutex> lk(g_scratch_mu);
+      st = scratch_for(m0->device, &sc);
+      if (st != RT_OK) return st;
+      if (n_path_rays > 0 && sc->path_cap < size_t(n_path_rays)) {
+        dev_free(sc->path_rays, sc->path_cap * sizeof(int32_t));
+        sc->path_rays = nullptr;
+        sc->path_cap = 0;
+        st = dev_alloc((void**)&sc->path_rays, size_t(n_path_rays) * sizeof(int32_t), "path rays");
+        if (st != RT_OK) return st;
+        sc->path_cap = size_t(n_path_rays);
+      }
+    }
+    TraceArgs a{};
+    a.g = m0->geom;
+    for (int k = 0; k < n_models; ++k) a.models[k] = {models[k]->nfg, models[k]->te};
+    for (int k = 0; k < n_freq; ++k) a.freqs[k] = freq_hz[k];
+    a.n_models = n_models;
+    a.n_freq = n_freq;
+    a.nu = I.nu; a.nv = I.nv;
+    a.tiles_u = (I.nu + kTile - 1) / kTile;
+    a.tiles_v = (I.nv + kTile - 1) / kTile;
+    a.tiles_per_image = a.tiles_u * a.tiles_v;
+    for (int k = 0; k < 3; ++k) { a.o[k] = o[k]; a.u[k] = u[k]; a.v[k] = v[k]; }
+    a.half_u = I.half_u; a.half_v = I.half_v;
+    a.ds_max = float(P.ds_max);
+    a.n_floor = float(P.n_floor);
+    a.ds_max_d = P.ds_max;
+    a.n_floor_d = P.n_floor;
+    a.eta = float(P.perturb_ratio);
+    a.max_steps = P.max_steps;
+    a.tb_inner = P.tb_inner_K;
+    a.tb_sky = P.tb_sky_K;
+    a.flags = P.flags;
+    a.tb = tb_out;
+    a.info = info_out;
+    a.stats = stats_out;
+    if (n_path_rays > 0) {
+      st = hip_check(hipMemcpyAsync(sc->path_rays, path_rays, size_t(n_path_rays) * sizeof(int32_t),
+                                    hipMemcpyHostToDevice, s), "copy path rays");
+      if (st == RT_OK) st = hip_check(hipStreamSynchronize(s), "path rays sync");
+      if (st != RT_OK) return st;
+      a.path_rays = sc->path_rays;
+      a.n_path = n_path_rays;
+      a.path_cap = path_capacity;
+      a.path_out = path_out;
+      a.path_len = path_len_out;
+    }
+    if (stats_out) {
+      st = hip_check(launch_fill_u32(reinterpret_cast<unsigned*>(stats_out), 0u, sizeof(rt_trace_stats) / 4, s), "stats fill");
+      if (st != RT_OK) return st;
+    }
+    const bool mixed = (P.flags & RT_PREC_ALL_FP32) == 0;
+    if (P.flags & RT_SCHED_PLAIN) {
+      const int waves = a.tiles_per_image;
+      const int blocks = (waves + 3) / 4;
+      for (int mi = 0; mi < n_models; ++mi)
+        for (int fi = 0; fi < n_freq; ++fi) {
+          a.image0 = mi * n_freq + fi;
+          st = hip_check(launch_trace(a, true, mixed, blocks, s), "trace launch");
+          if (st != RT_OK) return st;
+        }
+    } else {
+      unsigned slot;
+      {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        slot = sc->next_slot++ % kCounterSlots;
+      }
+      a.counters = sc->counters + size_t(slot) * kXcds;
+      a.n_bands = kXcds;
+      const int n_images = n_models * n_freq;
+      a.range_lo[0] = 0;
+      for (int x = 0; x < kXcds; ++x) {
+        const int row0 = (x * a.tiles_v) / kXcds, row1 = ((x + 1) * a.tiles_v) / kXcds;
+        a.range_lo[x + 1] = a.range_lo[x] + (row1 - row0) * a.tiles_u * n_images;
+      }
+      st = hip_check(launch_fill_u32(a.counters, 0u, kXcds, s), "counter fill");
+      if (st != RT_OK) return st;
+      const int per_cu = persistent_blocks_per_cu(mixed, a.g.kind);
+      long long blocks = (long long)sc->n_cu * per_cu;
+      const long long max_useful = ((long long)a.range_lo[kXcds] + 3) / 4;
+      if (blocks > max_useful) blocks = max_useful;
+      if (blocks < 1) blocks = 1;
+      st = hip_check(launch_trace(a, false, mixed, int(blocks), s), "persistent trace launch");
+      if (st != RT_OK) return st;
+    }
+    return RT_OK;
+  } catch (...) {
+    return fail(RT_E_INTERNAL, "unexpected exception");
+  }
+}
+
+rt_status rt_trace_adjoint(const rt_model* model, const double* freq_hz, int32_t n_freq, const rt_image_desc* image,
+                           const rt_params* params, const float* weights, double* loss_out, float* grad_ln_ne,
+                           float* grad_ln_te, float* tb_out, void* hip_stream) {
+  (void)model; (void)freq_hz; (void)n_freq; (void)image; (void)params; (void)weights; (void)loss_out;
+  (void)grad_ln_ne; (void)grad_ln_te; (void)tb_out; (void)hip_stream;
+  return fail(RT_E_UNSUPPORTED, "adjoint not built yet");
+}
+
+}  // extern "C"

@@ -1,0 +1,72 @@
+// Internal declarations shared by the C ABI layer and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/rtsun.h"
+
+namespace rt {
+
+constexpr int kMaxModels = 16;    // models per persistent launch
+constexpr int kMaxFreqs = 128;    // frequencies per persistent launch
+constexpr int kTile = 8;          // 8 x 8 pixels per wave64
+constexpr int kXcds = 8;          // MI355X: 8 accelerator complex dies, blocks dealt round-robin
+constexpr int kPathStride = 9;    // x y z s lnM dlnS/ds tau ne te
+
+// Grid geometry common to every model of a call.
+struct DevGeom {
+  int kind;             // rt_grid_kind
+  int n0, n1, n2, n2p;  // n2p: row length of the packed arrays (n2 + 1 for the periodic phi axis)
+  float ln_rin, inv_dl, inv_dth, inv_dph;  // spherical
+  float org[3], inv_sp[3];                 // Cartesian
+  double ln_rin_d, inv_dl_d, inv_dth_d, inv_dph_d;
+  double org_d[3], inv_sp_d[3];
+  double r_in, r_max;
+  int has_inner;
+};
+
+struct DevModelPtrs {
+  const float4* nfg;    // per vertex: n_e, dn/dxi_0, dn/dxi_1, dn/dxi_2 (index-space gradient)
+  const float* te;      // per vertex: T
+};
+
+struct TraceArgs {
+  DevGeom g;
+  DevModelPtrs models[kMaxModels];
+  double freqs[kMaxFreqs];
+  int n_models, n_freq;
+  int nu, nv, tiles_u, tiles_v, tiles_per_image;
+  int image0;                 // plain launches: flat (model * n_freq + freq) index of the image
+  double o[3], u[3], v[3];    // observer axes
+  double half_u, half_v;
+  float ds_max, n_floor, eta;
+  double ds_max_d, n_floor_d;
+  int max_steps;
+  double tb_inner, tb_sky;
+  uint32_t flags;
+  float* tb;
+  rt_ray_info* info;
+  rt_trace_stats* stats;
+  const int32_t* path_rays;
+  int n_path, path_cap;
+  float* path_out;
+  int32_t* path_len;
+  // persistent scheduling: tiles are split into kXcds contiguous ranges
+  unsigned* counters;         // kXcds claim counters (zeroed before launch)
+  int range_lo[kXcds + 1];
+  int n_bands;                // image rows split into bands, one per range
+};
+
+// Launchers (rt_kernels.hip).
+hipError_t launch_pack(const DevGeom& g, const float* ne, const float* te, float4* nfg, float* te_out,
+                       hipStream_t s);
+hipError_t launch_validate(const float* ne, const float* te, long long n, int* bad, hipStream_t s);
+hipError_t launch_fill_u32(unsigned* p, unsigned val, long long n, hipStream_t s);
+hipError_t launch_trace(const TraceArgs& a, bool plain, bool mixed, int grid_blocks, hipStream_t s);
+int persistent_blocks_per_cu(bool mixed, int kind);
+
+}  // namespace rt
+
+static_assert(sizeof(rt_ray_info) == 32, "rt_ray_info is 32 bytes");
+static_assert(sizeof(rt_trace_stats) == 40, "rt_trace_stats is 40 bytes");

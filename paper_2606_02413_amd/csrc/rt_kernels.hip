@@ -1,0 +1,284 @@
+// Kernels: model staging, value validation, and the ray tracer in its two
+// launch forms (one launch per image, or one persistent launch with lane refill).
+#include <hip/hip_runtime.h>
+
+#include "rt_internal.hpp"
+#include "rt_trace.hpp"
+
+namespace rt {
+
+// ---------------------------------------------------------------------------
+// Model staging: C-order [n0][n1][n2] n_e, T  ->  packed rows of n2p vertices
+// holding (n_e, dn/dxi_0, dn/dxi_1, dn/dxi_2) and T.  The index-space vertex
+// gradient is the central difference (one-sided at non-periodic edges); for
+// spherical grids the phi axis is periodic and row element n2 repeats element 0,
+// so a cell's two phi corners are always adjacent in memory.
+// ---------------------------------------------------------------------------
+__global__ void k_pack(DevGeom g, const float* __restrict__ ne, const float* __restrict__ te, float4* __restrict__ nfg,
+                       float* __restrict__ te_out) {
+  const long long total = (long long)g.n0 * g.n1 * g.n2p;
+  for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (long long)gridDim.x * blockDim.x) {
+    const int cp = int(idx % g.n2p);
+    const long long ab = idx / g.n2p;
+    const int b = int(ab % g.n1);
+    const int a = int(ab / g.n1);
+    const bool periodic = g.kind == RT_GRID_SPHERICAL_LOGR;
+    const int c = (cp == g.n2) ? 0 : cp;  // only reached for the periodic wrap column
+    auto at = [&](int i, int j, int k) -> float { return ne[((long long)i * g.n1 + j) * g.n2 + k]; };
+    float d0, d1, d2;
+    if (a == 0) d0 = at(1, b, c) - at(0, b, c);
+    else if (a == g.n0 - 1) d0 = at(g.n0 - 1, b, c) - at(g.n0 - 2, b, c);
+    else d0 = 0.5f * (at(a + 1, b, c) - at(a - 1, b, c));
+    if (b == 0) d1 = at(a, 1, c) - at(a, 0, c);
+    else if (b == g.n1 - 1) d1 = at(a, g.n1 - 1, c) - at(a, g.n1 - 2, c);
+    else d1 = 0.5f * (at(a, b + 1, c) - at(a, b - 1, c));
+    if (periodic) {
+      const int cm = (c == 0) ? g.n2 - 1 : c - 1;
+      const int cq = (c == g.n2 - 1) ? 0 : c + 1;
+      d2 = 0.5f * (at(a, b, cq) - at(a, b, cm));
+    } else if (c == 0) {
+      d2 = at(a, b, 1) - at(a, b, 0);
+    } else if (c == g.n2 - 1) {
+      d2 = at(a, b, g.n2 - 1) - at(a, b, g.n2 - 2);
+    } else {
+      d2 = 0.5f * (at(a, b, c + 1) - at(a, b, c - 1));
+    }
+    nfg[idx] = make_float4(at(a, b, c), d0, d1, d2);
+    te_out[idx] = te[((long long)a * g.n1 + b) * g.n2 + c];
+  }
+}
+
+__global__ void k_validate(const float* __restrict__ ne, const float* __restrict__ te, long long n, int* bad) {
+  int cnt = 0;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    const float x = ne[i], t = te[i];
+    if (!(isfinite(x) && x >= 0.0f && isfinite(t) && t > 0.0f)) ++cnt;
+  }
+  if (cnt) atomicAdd(bad, cnt);
+}
+
+__global__ void k_fill_u32(unsigned* p, unsigned v, long long n) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+// ---------------------------------------------------------------------------
+// Per-wave statistics.
+// ---------------------------------------------------------------------------
+struct LaneStats {
+  unsigned long long steps;
+  unsigned max_steps;
+  unsigned count[6];
+};
+
+__device__ __forceinline__ void lane_stats_add(LaneStats& s, int n, int code) {
+  s.steps += (unsigned long long)n;
+  s.max_steps = max(s.max_steps, (unsigned)n);
+#pragma unroll
+  for (int k = 0; k < 6; ++k) s.count[k] += (code == k) ? 1u : 0u;
+}
+
+__device__ void wave_stats_flush(const LaneStats& s, rt_trace_stats* out) {
+  if (!out) return;
+  unsigned long long st = s.steps;
+  unsigned mx = s.max_steps;
+  unsigned c[6];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) c[k] = s.count[k];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    st += __shfl_xor(st, off);
+    mx = max(mx, (unsigned)__shfl_xor((int)mx, off));
+#pragma unroll
+    for (int k = 0; k < 6; ++k) c[k] += (unsigned)__shfl_xor((int)c[k], off);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    atomicAdd(&out->ray_steps, st);
+    atomicMax(&out->max_steps, mx);
+#pragma unroll
+    for (int k = 0; k < 6; ++k)
+      if (c[k]) atomicAdd(&out->code_count[k], c[k]);
+  }
+}
+
+// Blocks are dealt to the 8 dies round-robin; give each die a contiguous run of
+// logical blocks (a band of image rows) so that its L2 sees neighbouring rays.
+__device__ __forceinline__ int xcd_remap(int bid, int nblocks) {
+  const int x = bid % kXcds, k = bid / kXcds;
+  const int per = nblocks / kXcds, rem = nblocks % kXcds;
+  return (x < rem) ? x * (per + 1) + k : rem * (per + 1) + (x - rem) * per + k;
+}
+
+// ---------------------------------------------------------------------------
+// One launch per (model, frequency) image: a wave traces one 8x8 pixel tile.
+// ---------------------------------------------------------------------------
+template <bool MIXED, int KIND>
+__global__ __launch_bounds__(256) void k_trace_plain(TraceArgs a) {
+  __shared__ float4 lds_c[4][8][kWaveLanes];
+  __shared__ float lds_t[4][8][kWaveLanes];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int tile = xcd_remap(blockIdx.x, gridDim.x) * 4 + wave;
+  const int ty = tile / a.tiles_u, tx = tile - ty * a.tiles_u;
+  if (ty >= a.tiles_v) return;  // whole wave
+  const int j = tx * kTile + (lane & 7), i = ty * kTile + (lane >> 3);
+  LaneStats st{};
+  if (i < a.nv && j < a.nu) {
+    const int id = a.image0 * (a.nu * a.nv) + i * a.nu + j;
+    RayState R;
+    CellCache C;
+    C.key = -1;
+    C.c = &lds_c[wave][0][lane];
+    C.t = &lds_t[wave][0][lane];
+    if (init_ray<KIND>(a, id, R, C)) {
+      int code;
+      do {
+        code = ray_step<MIXED, KIND>(a, R, C);
+      } while (code == kRunning);
+      lane_stats_add(st, R.n, code);
+    } else {
+      lane_stats_add(st, 0, kMiss);
+    }
+  }
+  wave_stats_flush(st, a.stats);
+}
+
+// Persistent launch over all (model, frequency, tile) work.  Tiles are split
+// into kXcds ranges (one band of image rows of every image each); a wave claims
+// a tile from its home range (then from the others) and hands its 64 rays to
+// idle lanes in lane order.  A lane whose ray has finished takes the next ray at
+// the following step, so lanes stay busy while rays of very different lengths
+// finish at different times.  The loop ends when every range is exhausted and no
+// lane holds a ray; each ray takes at most max_steps steps, so every wave ends.
+__device__ __forceinline__ int tile_slot_ray(const TraceArgs& a, int t, int slot) {
+  int x = 0;
+  while (x < kXcds - 1 && t >= a.range_lo[x + 1]) ++x;
+  const int local = t - a.range_lo[x];
+  const int row0 = (x * a.tiles_v) / a.n_bands;
+  const int row1 = ((x + 1) * a.tiles_v) / a.n_bands;
+  const int per_image = (row1 - row0) * a.tiles_u;
+  const int img = local / per_image;
+  const int rem = local - img * per_image;
+  const int ty = row0 + rem / a.tiles_u;
+  const int tx = rem - (rem / a.tiles_u) * a.tiles_u;
+  const int i = ty * kTile + (slot >> 3), j = tx * kTile + (slot & 7);
+  if (i >= a.nv || j >= a.nu) return -1;
+  return img * (a.nu * a.nv) + i * a.nu + j;
+}
+
+template <bool MIXED, int KIND>
+__global__ __launch_bounds__(256) void k_trace_persistent(TraceArgs a) {
+  __shared__ float4 lds_c[4][8][kWaveLanes];
+  __shared__ float lds_t[4][8][kWaveLanes];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int home = blockIdx.x % kXcds;
+  unsigned exhausted = 0;
+  int pool_left = 0, cur_tile = -1;
+  bool active = false;
+  RayState R;
+  CellCache C;
+  C.key = -1;
+  C.c = &lds_c[wave][0][lane];
+  C.t = &lds_t[wave][0][lane];
+  LaneStats st{};
+  const unsigned all = (1u << kXcds) - 1u;
+  for (;;) {
+    unsigned long long idle = __ballot(!active);
+    while (idle != 0ull && (pool_left > 0 || exhausted != all)) {
+      if (pool_left == 0) {
+        int t = -1;
+        for (int k = 0; k < kXcds && t < 0; ++k) {
+          const int x = (home + k) % kXcds;
+          if (exhausted & (1u << x)) continue;
+          unsigned got = 0;
+          if (lane == 0) got = atomicAdd(&a.counters[x], 1u);
+          got = (unsigned)__shfl((int)got, 0);
+          const int len = a.range_lo[x + 1] - a.range_lo[x];
+          if ((int)got < len) t = a.range_lo[x] + (int)got;
+          else exhausted |= 1u << x;
+        }
+        if (t < 0) break;
+        cur_tile = t;
+        pool_left = 64;
+      }
+      const int rank = __popcll(idle & ((1ull << lane) - 1ull));
+      const int take = min(__popcll(idle), pool_left);
+      if (!active && rank < take) {
+        const int id = tile_slot_ray(a, cur_tile, (64 - pool_left) + rank);
+        if (id >= 0) {
+          if (init_ray<KIND>(a, id, R, C)) active = true;
+          else lane_stats_add(st, 0, kMiss);
+        }
+      }
+      pool_left -= take;
+      idle = __ballot(!active);
+    }
+    if (__ballot(active) == 0ull) break;
+    if (active) {
+      const int code = ray_step<MIXED, KIND>(a, R, C);
+      if (code != kRunning) {
+        active = false;
+        lane_stats_add(st, R.n, code);
+      }
+    }
+  }
+  wave_stats_flush(st, a.stats);
+}
+
+// ---------------------------------------------------------------------------
+// Launchers.
+// ---------------------------------------------------------------------------
+static int grid_for(long long n, int threads) {
+  long long b = (n + threads - 1) / threads;
+  if (b > 65536) b = 65536;
+  if (b < 1) b = 1;
+  return int(b);
+}
+
+hipError_t launch_pack(const DevGeom& g, const float* ne, const float* te, float4* nfg, float* te_out, hipStream_t s) {
+  const long long total = (long long)g.n0 * g.n1 * g.n2p;
+  hipLaunchKernelGGL(k_pack, dim3(grid_for(total, 256)), dim3(256), 0, s, g, ne, te, nfg, te_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_validate(const float* ne, const float* te, long long n, int* bad, hipStream_t s) {
+  hipLaunchKernelGGL(k_validate, dim3(grid_for(n, 256)), dim3(256), 0, s, ne, te, n, bad);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(unsigned* p, unsigned val, long long n, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(n, 256)), dim3(256), 0, s, p, val, n);
+  return hipGetLastError();
+}
+
+template <bool MIXED, int KIND>
+static hipError_t launch_one(const TraceArgs& a, bool plain, int blocks, hipStream_t s) {
+  if (plain) hipLaunchKernelGGL((k_trace_plain<MIXED, KIND>), dim3(blocks), dim3(256), 0, s, a);
+  else hipLaunchKernelGGL((k_trace_persistent<MIXED, KIND>), dim3(blocks), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_trace(const TraceArgs& a, bool plain, bool mixed, int blocks, hipStream_t s) {
+  const bool sph = a.g.kind == RT_GRID_SPHERICAL_LOGR;
+  if (mixed) return sph ? launch_one<true, RT_GRID_SPHERICAL_LOGR>(a, plain, blocks, s)
+                        : launch_one<true, RT_GRID_CARTESIAN>(a, plain, blocks, s);
+  return sph ? launch_one<false, RT_GRID_SPHERICAL_LOGR>(a, plain, blocks, s)
+             : launch_one<false, RT_GRID_CARTESIAN>(a, plain, blocks, s);
+}
+
+int persistent_blocks_per_cu(bool mixed, int kind) {
+  int n = 0;
+  hipError_t e;
+  const bool sph = kind == RT_GRID_SPHERICAL_LOGR;
+  if (mixed) {
+    e = sph ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_trace_persistent<true, RT_GRID_SPHERICAL_LOGR>, 256, 0)
+            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_trace_persistent<true, RT_GRID_CARTESIAN>, 256, 0);
+  } else {
+    e = sph ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_trace_persistent<false, RT_GRID_SPHERICAL_LOGR>, 256, 0)
+            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_trace_persistent<false, RT_GRID_CARTESIAN>, 256, 0);
+  }
+  if (e != hipSuccess || n < 1) n = 1;
+  return n;
+}
+
+}  // namespace rt

@@ -1,0 +1,241 @@
+"""Python binding of the HIP library's C ABI (argument marshalling only).
+
+Every step of the ray tracing runs in the HIP kernels of ``librtsun.so``; this
+module only fills the ABI structs, passes torch device pointers and the current
+HIP stream, and raises on a non-OK status.  There is no CPU fallback: if the
+library is missing the import of ``lib()`` raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librtsun.so")
+ABI_VERSION = 1
+
+RT_GRID_SPHERICAL_LOGR, RT_GRID_CARTESIAN = 0, 1
+RT_USE_MAGNIFICATION = 1 << 0
+RT_USE_REFRACTION = 1 << 1
+RT_PREC_ALL_FP32 = 1 << 2
+RT_SCHED_PLAIN = 1 << 3
+RT_DETERMINISTIC_GRAD = 1 << 4
+RT_TEST_NO_ABSORPTION = 1 << 30
+
+EXIT_OUTER, HIT_INNER, MISS, MAX_STEPS, NONFINITE = 1, 2, 3, 4, 5
+FLAG_MARGINAL = 2
+PATH_FIELDS = ("x", "y", "z", "s", "ln_m", "dlns_ds", "tau", "ne", "te")
+
+STATUS = {0: "RT_OK", 1: "RT_E_INVALID_ARG", 2: "RT_E_NONFINITE_INPUT", 3: "RT_E_OUT_OF_MEMORY",
+          4: "RT_E_DEVICE", 5: "RT_E_UNSUPPORTED", 6: "RT_E_CAPACITY", 7: "RT_E_INTERNAL"}
+
+
+class RtError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class GridDesc(C.Structure):
+    _fields_ = [("abi_version", C.c_uint32), ("kind", C.c_uint32), ("n0", C.c_int32), ("n1", C.c_int32),
+                ("n2", C.c_int32), ("_reserved", C.c_int32), ("r_in", C.c_double), ("r_max", C.c_double),
+                ("origin", C.c_double * 3), ("spacing", C.c_double * 3)]
+
+
+class ImageDesc(C.Structure):
+    _fields_ = [("obs_dir", C.c_double * 3), ("up", C.c_double * 3), ("nu", C.c_int32), ("nv", C.c_int32),
+                ("half_u", C.c_double), ("half_v", C.c_double)]
+
+
+class Params(C.Structure):
+    _fields_ = [("abi_version", C.c_uint32), ("flags", C.c_uint32), ("ds_max", C.c_double),
+                ("n_floor", C.c_double), ("max_steps", C.c_int32), ("checkpoint_every", C.c_int32),
+                ("perturb_ratio", C.c_double), ("tb_inner_K", C.c_double), ("tb_sky_K", C.c_double)]
+
+
+INFO_DTYPE = np.dtype([("n_steps", "<i4"), ("code", "i1"), ("flags", "i1"), ("_pad", "i1", (2,)),
+                       ("exit_pos", "<f4", (3,)), ("tau", "<f4"), ("ln_s_end", "<f4"), ("r_min", "<f4")])
+STATS_DTYPE = np.dtype([("ray_steps", "<u8"), ("max_steps", "<u4"), ("code_count", "<u4", (6,)), ("_pad", "<u4")])
+assert INFO_DTYPE.itemsize == 32 and STATS_DTYPE.itemsize == 40
+
+_lib = None
+
+
+def lib():
+    """Load librtsun.so (built in-tree by __graft_entry__.build())."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"HIP library not built: {LIB_PATH} is missing (run __graft_entry__.build())")
+        L = C.CDLL(LIB_PATH)
+        vp = C.c_void_p
+        L.rt_model_load.argtypes = [C.POINTER(GridDesc), vp, vp, C.c_int32, vp, C.POINTER(vp)]
+        L.rt_model_load.restype = C.c_int
+        L.rt_model_update.argtypes = [vp, vp, vp, C.c_int32, vp]
+        L.rt_model_update.restype = C.c_int
+        L.rt_model_free.argtypes = [vp]
+        L.rt_model_free.restype = None
+        L.rt_trace_maps.argtypes = [C.POINTER(vp), C.c_int32, C.POINTER(C.c_double), C.c_int32,
+                                    C.POINTER(ImageDesc), C.POINTER(Params), vp, vp, vp, C.POINTER(C.c_int32),
+                                    C.c_int32, C.c_int32, vp, vp, vp]
+        L.rt_trace_maps.restype = C.c_int
+        L.rt_trace_adjoint.argtypes = [vp, C.POINTER(C.c_double), C.c_int32, C.POINTER(ImageDesc),
+                                       C.POINTER(Params), vp, vp, vp, vp, vp, vp]
+        L.rt_trace_adjoint.restype = C.c_int
+        L.rt_status_string.argtypes = [C.c_int]
+        L.rt_status_string.restype = C.c_char_p
+        L.rt_last_error_message.argtypes = []
+        L.rt_last_error_message.restype = C.c_char_p
+        L.rt_abi_version.argtypes = []
+        L.rt_abi_version.restype = C.c_uint32
+        L.rt_params_default.argtypes = [C.POINTER(Params)]
+        L.rt_params_default.restype = None
+        _lib = L
+    return _lib
+
+
+def _check(status):
+    if status != 0:
+        raise RtError(status, lib().rt_last_error_message().decode())
+
+
+def _stream_ptr(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def grid_desc(kind, shape, r_in, r_max, origin=(0.0, 0.0, 0.0), spacing=(1.0, 1.0, 1.0)):
+    d = GridDesc()
+    d.abi_version = ABI_VERSION
+    d.kind = kind
+    d.n0, d.n1, d.n2 = (int(x) for x in shape)
+    d._reserved = 0
+    d.r_in, d.r_max = float(r_in), float(r_max)
+    d.origin = (C.c_double * 3)(*origin)
+    d.spacing = (C.c_double * 3)(*spacing)
+    return d
+
+
+def image_desc(n, half_width, obs_dir=(1.0, 0.0, 0.0), up=(0.0, 0.0, 1.0), nv=None, half_v=None):
+    im = ImageDesc()
+    im.obs_dir = (C.c_double * 3)(*obs_dir)
+    im.up = (C.c_double * 3)(*up)
+    im.nu = int(n)
+    im.nv = int(n if nv is None else nv)
+    im.half_u = float(half_width)
+    im.half_v = float(half_width if half_v is None else half_v)
+    return im
+
+
+def params(*, ds_max=0.005, n_floor=1.0, max_steps=200000, eta=1e-2, tb_inner=1.0e4, tb_sky=0.0,
+           refraction=True, magnification=True, all_fp32=False, plain=False, no_absorption=False,
+           checkpoint_every=64):
+    p = Params()
+    lib().rt_params_default(C.byref(p))
+    f = 0
+    f |= RT_USE_REFRACTION if refraction else 0
+    f |= RT_USE_MAGNIFICATION if magnification else 0
+    f |= RT_PREC_ALL_FP32 if all_fp32 else 0
+    f |= RT_SCHED_PLAIN if plain else 0
+    f |= RT_TEST_NO_ABSORPTION if no_absorption else 0
+    p.flags = f
+    p.ds_max, p.n_floor, p.max_steps = float(ds_max), float(n_floor), int(max_steps)
+    p.perturb_ratio, p.tb_inner_K, p.tb_sky_K = float(eta), float(tb_inner), float(tb_sky)
+    p.checkpoint_every = int(checkpoint_every)
+    return p
+
+
+class Model:
+    """A model loaded on a device (owns the library's rt_model)."""
+
+    def __init__(self, desc, ne, te, device=0, stream=None):
+        ne = np.ascontiguousarray(ne, dtype=np.float32)
+        te = np.ascontiguousarray(te, dtype=np.float32)
+        self.desc = desc
+        self.shape = (desc.n0, desc.n1, desc.n2)
+        if ne.size != desc.n0 * desc.n1 * desc.n2 or te.size != ne.size:
+            raise ValueError("array sizes do not match the descriptor")
+        h = C.c_void_p()
+        s = _stream_ptr(stream) if stream is not False else C.c_void_p(0)
+        _check(lib().rt_model_load(C.byref(desc), ne.ctypes.data_as(C.c_void_p), te.ctypes.data_as(C.c_void_p),
+                                   int(device), s, C.byref(h)))
+        self.handle = h
+        self.device = device
+
+    @classmethod
+    def from_corona(cls, cor, device=0):
+        d = grid_desc(RT_GRID_SPHERICAL_LOGR, cor.shape, cor.r_in, cor.r_max)
+        return cls(d, cor.ne, cor.te, device)
+
+    def update_device(self, ne_t, te_t, stream=None):
+        """Replace values from torch device tensors (float32, C-order, same shape)."""
+        assert ne_t.is_contiguous() and te_t.is_contiguous()
+        _check(lib().rt_model_update(self.handle, C.c_void_p(ne_t.data_ptr()), C.c_void_p(te_t.data_ptr()), 1,
+                                     _stream_ptr(stream)))
+
+    def update_host(self, ne, te, stream=None):
+        ne = np.ascontiguousarray(ne, dtype=np.float32)
+        te = np.ascontiguousarray(te, dtype=np.float32)
+        _check(lib().rt_model_update(self.handle, ne.ctypes.data_as(C.c_void_p), te.ctypes.data_as(C.c_void_p), 0,
+                                     _stream_ptr(stream)))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().rt_model_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def trace_maps(models, freqs, image, prm, *, info=True, stats=True, path_rays=None, path_capacity=0,
+               stream=None, out=None):
+    """Trace all (model, frequency) maps.  Returns a dict of torch tensors on the device:
+    tb [M][F][nv][nu] float32, info [...][32] uint8 (decode with decode_info), stats [40] uint8,
+    path [P][cap][9] float32 and path_len [P] int32 when path_rays is given."""
+    import torch
+    if isinstance(models, Model):
+        models = [models]
+    freqs = np.ascontiguousarray(np.atleast_1d(freqs), dtype=np.float64)
+    M, F = len(models), freqs.shape[0]
+    dev = torch.device("cuda", models[0].device)
+    shape = (M, F, image.nv, image.nu)
+    res = {} if out is None else out
+    if "tb" not in res:
+        res["tb"] = torch.empty(shape, dtype=torch.float32, device=dev)
+    if info and "info" not in res:
+        res["info"] = torch.empty(shape + (32,), dtype=torch.uint8, device=dev)
+    if stats and "stats" not in res:
+        res["stats"] = torch.empty(40, dtype=torch.uint8, device=dev)
+    handles = (C.c_void_p * M)(*[m.handle.value for m in models])
+    n_path = 0
+    pr = None
+    if path_rays is not None and len(path_rays) > 0:
+        pr = np.ascontiguousarray(np.sort(np.asarray(path_rays, dtype=np.int32)))
+        n_path = pr.shape[0]
+        res["path"] = torch.zeros((n_path, path_capacity, 9), dtype=torch.float32, device=dev)
+        res["path_len"] = torch.zeros(n_path, dtype=torch.int32, device=dev)
+    ptr = lambda k: C.c_void_p(res[k].data_ptr()) if k in res and res[k] is not None else C.c_void_p(0)
+    _check(lib().rt_trace_maps(handles, M, freqs.ctypes.data_as(C.POINTER(C.c_double)), F, C.byref(image),
+                               C.byref(prm), ptr("tb"), ptr("info") if info else C.c_void_p(0),
+                               ptr("stats") if stats else C.c_void_p(0),
+                               pr.ctypes.data_as(C.POINTER(C.c_int32)) if n_path else None, n_path,
+                               int(path_capacity), ptr("path") if n_path else C.c_void_p(0),
+                               ptr("path_len") if n_path else C.c_void_p(0), _stream_ptr(stream)))
+    return res
+
+
+def decode_info(info_t):
+    """Device uint8 [..., 32] tensor -> numpy structured array of INFO_DTYPE."""
+    a = info_t.detach().cpu().numpy()
+    return a.reshape(-1, 32).copy().view(INFO_DTYPE).reshape(a.shape[:-1])
+
+
+def decode_stats(stats_t):
+    return stats_t.detach().cpu().numpy().copy().view(STATS_DTYPE)[0]

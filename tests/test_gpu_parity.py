@@ -1,0 +1,169 @@
+"""GPU path vs the FP64 oracle, element by element, through the C ABI.
+
+Each case prints its label before the GPU call so that a failure names it.
+"""
+import numpy as np
+import pytest
+
+from paper_2606_02413_amd import corona
+from tests import parity_util as PU
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def R():
+    if not PU.gpu_available():
+        pytest.skip("no GPU")
+    from paper_2606_02413_amd import rtsun
+    return rtsun
+
+
+@pytest.fixture(scope="module")
+def small_model(R):
+    cor = corona.spherically_symmetric()
+    return cor, R.Model.from_corona(cor)
+
+
+@pytest.fixture(scope="module")
+def structured_small(R):
+    cor = corona.structured(nr=64, nt=32, nph=64, r_in=1.0, r_max=30.0, seed=11, n_ar=4, n_feat=256)
+    return cor, R.Model.from_corona(cor)
+
+
+def test_small_workload_full_map(R, orc, small_model):
+    """Spherically symmetric Baumbach-Allen, 64x32x64, 64^2 image, 150 MHz, fixed dt = 0.005."""
+    cor, m = small_model
+    kw = PU.step_kwargs(0.005, 1.0)
+    print("case small full map", flush=True)
+    g = PU.gpu_trace([m], [150e6], 64, 2.5, kw, plain=True)
+    pix = np.arange(64 * 64, dtype=np.int32)
+    o = PU.oracle_trace(orc, cor, 150e6, 64, 2.5, pix, kw)
+    s = PU.compare(g["tb"].reshape(-1), g["info"].reshape(-1), o, label="small")
+    assert s["flagged"] < 0.05 * s["n"]
+    st = g["stats"]
+    assert st["ray_steps"] == int(g["info"]["n_steps"].sum())
+    assert st["code_count"][3] == int((o["code"] == 3).sum())
+
+
+@pytest.mark.parametrize("freq", [40e6, 80e6, 300e6])
+def test_small_workload_frequencies(R, orc, small_model, freq):
+    cor, m = small_model
+    kw = PU.step_kwargs(0.005, 1.0)
+    print(f"case small f={freq}", flush=True)
+    g = PU.gpu_trace([m], [freq], 64, 2.5, kw)
+    pix = np.arange(0, 64 * 64, 3, dtype=np.int32)
+    o = PU.oracle_trace(orc, cor, freq, 64, 2.5, pix, kw)
+    PU.compare(g["tb"].reshape(-1)[pix], g["info"].reshape(-1)[pix], o, label=f"small-{freq/1e6:.0f}MHz")
+
+
+def test_persistent_equals_plain_bitwise(R, structured_small):
+    cor, m = structured_small
+    kw = PU.step_kwargs(0.01, 0.1)
+    freqs = corona.log_freqs(3)
+    print("case persistent vs plain", flush=True)
+    a = PU.gpu_trace([m, m], freqs, 45, 3.0, kw, plain=True)
+    b = PU.gpu_trace([m, m], freqs, 45, 3.0, kw, plain=False)
+    assert np.array_equal(a["tb"].view(np.uint32), b["tb"].view(np.uint32))
+    assert np.array_equal(a["info"].view(np.uint8), b["info"].view(np.uint8))
+    assert a["stats"]["ray_steps"] == b["stats"]["ray_steps"]
+
+
+@pytest.mark.parametrize("adaptive", [False, True])
+def test_structured_ragged_image(R, orc, structured_small, adaptive):
+    """Random-field corona with active regions, r 1-30, ragged 37x29 image (tiles with a tail)."""
+    cor, m = structured_small
+    kw = PU.step_kwargs(0.01, 0.1 if adaptive else 1.0)
+    freqs = [40e6, 150e6, 800e6]
+    nu, nv = 37, 29
+    im_g = R.image_desc(nu, 3.0, nv=nv, half_v=2.4)
+    print(f"case structured ragged adaptive={adaptive}", flush=True)
+    g = PU.gpu_trace([m], freqs, nu, 3.0, kw, image=im_g)
+    im_o = orc.make_image(nu, 3.0, nv=nv, half_v=2.4)
+    pix = np.arange(nu * nv, dtype=np.int32)
+    for k, f in enumerate(freqs):
+        o = PU.oracle_trace(orc, cor, f, nu, 3.0, pix, kw, image=im_o)
+        PU.compare(g["tb"][0, k].reshape(-1), g["info"][0, k].reshape(-1), o, label=f"ragged-{f/1e6:.0f}")
+
+
+def test_los_and_no_magnification_modes(R, orc, structured_small):
+    cor, m = structured_small
+    pix = np.arange(0, 32 * 32, 2, dtype=np.int32)
+    for refr, mag in ((False, False), (True, False)):
+        kw = PU.step_kwargs(0.01, 0.1, refraction=refr, magnification=mag)
+        print(f"case modes refraction={refr} magnification={mag}", flush=True)
+        g = PU.gpu_trace([m], [60e6], 32, 2.0, kw)
+        o = PU.oracle_trace(orc, cor, 60e6, 32, 2.0, pix, kw)
+        PU.compare(g["tb"].reshape(-1)[pix], g["info"].reshape(-1)[pix], o, label=f"modes-{refr}-{mag}")
+        if not mag:
+            assert np.all(g["info"]["ln_s_end"] == 0)
+
+
+def test_flux_tube_identity_on_gpu(R, structured_small):
+    """kappa = 0, equal boundary temperatures: T_b = T0 exp(ln S_end/S_0) (Eq. 1)."""
+    cor, m = structured_small
+    kw = PU.step_kwargs(0.01, 0.1, no_absorption=True, tb_inner=5e5, tb_sky=5e5)
+    print("case flux tube", flush=True)
+    g = PU.gpu_trace([m], [60e6], 32, 2.0, kw)
+    info = g["info"].reshape(-1)
+    hit = info["code"] != 3
+    want = 5e5 * np.exp(info["ln_s_end"][hit].astype(np.float64))
+    assert np.max(np.abs(g["tb"].reshape(-1)[hit] / want - 1)) < 1e-5
+
+
+def test_max_steps_and_miss(R, orc, small_model):
+    cor, m = small_model
+    kw = PU.step_kwargs(0.005, 1.0, max_steps=37)
+    print("case max_steps", flush=True)
+    g = PU.gpu_trace([m], [150e6], 16, 2.5, kw)
+    o = PU.oracle_trace(orc, cor, 150e6, 16, 2.5, np.arange(256, dtype=np.int32), kw)
+    PU.compare(g["tb"].reshape(-1), g["info"].reshape(-1), o, label="max-steps")
+    assert (g["info"]["code"] == 4).any() and (g["info"]["code"] == 3).any()
+    assert g["info"]["n_steps"].max() == 37
+
+
+def test_cartesian_grid_parabola(R, orc):
+    """Linear slab on a Cartesian grid: GPU and oracle parity on the exact parabola case."""
+    n = 25
+    k = np.arange(n)
+    ne = np.broadcast_to((1e6 + 5e4 * k)[None, None, :], (n, n, n)).astype(np.float32).copy()
+    te = np.full((n, n, n), 1e6, np.float32)
+    d = R.grid_desc(R.RT_GRID_CARTESIAN, (n, n, n), -1.0, 5.0, origin=(-6, -6, -6), spacing=(0.5, 0.5, 0.5))
+    m = R.Model(d, ne, te)
+    kw = PU.step_kwargs(0.01, 1.0)
+    print("case cartesian", flush=True)
+    g = PU.gpu_trace([m], [20e6], 16, 3.0, kw)
+    med = orc.OracleMedium(orc.GRID_CARTESIAN, shape=(n, n, n), r_in=-1.0, r_max=5.0, ne=ne, te=te,
+                           origin=(-6, -6, -6), spacing=(0.5, 0.5, 0.5))
+    o = orc.trace_pixels(med, orc.make_params(**kw), orc.make_image(16, 3.0), 20e6, np.arange(256, dtype=np.int32))
+    PU.compare(g["tb"].reshape(-1), g["info"].reshape(-1), o, label="cartesian")
+    m.close()
+
+
+def test_path_output_matches_oracle(R, orc, small_model):
+    cor, m = small_model
+    kw = PU.step_kwargs(0.005, 1.0)
+    rays = [32 * 64 + 30, 10 * 64 + 12]
+    print("case paths", flush=True)
+    g = PU.gpu_trace([m], [80e6], 64, 2.5, kw, path_rays=rays, path_capacity=2000)
+    med = orc.OracleMedium.from_corona(cor)
+    for slot, ray in enumerate(sorted(rays)):
+        res, path = orc.trace_pixel_path(med, orc.make_params(**kw), orc.make_image(64, 2.5), 80e6, ray)
+        n = int(g["path_len"][slot])
+        assert n == len(path) == res["n_steps"]
+        gp = g["path"][slot, :n]
+        assert np.max(np.abs(gp[:, :3] - path[:, :3])) < 1e-5
+        assert np.max(np.abs(gp[:, 6] - path[:, 6]) / np.maximum(path[:, 6], 1e-6)) < 1e-3
+
+
+def test_all_fp32_variant_close(R, orc, structured_small):
+    cor, m = structured_small
+    kw = PU.step_kwargs(0.01, 0.1)
+    print("case all-fp32", flush=True)
+    g = PU.gpu_trace([m], [100e6], 24, 2.0, kw, all_fp32=True)
+    pix = np.arange(24 * 24, dtype=np.int32)
+    o = PU.oracle_trace(orc, cor, 100e6, 24, 2.0, pix, kw)
+    ok = o["flags"] == 0
+    rel = np.abs(g["tb"].reshape(-1) - o["tb"]) / np.maximum(o["tb"], 1.0)
+    print("all-fp32 max rel", rel[ok].max(), "median", np.median(rel[ok]))
+    assert rel[ok].max() < 5e-2
