@@ -68,6 +68,10 @@ struct DeviceScratch {
   unsigned next_slot = 0;
   int32_t* path_rays = nullptr;
   size_t path_cap = 0;
+  double* start_idx = nullptr;   // per-pixel start grid index, grown on demand
+  size_t start_cap = 0;          // pixels
+  float* start_ne = nullptr;     // per-(model, pixel) n_e at the start point
+  size_t start_ne_cap = 0;
   int n_cu = 0;
 };
 constexpr unsigned kCounterSlots = 1024;
@@ -393,6 +397,23 @@ rt_status rt_trace_maps(const rt_model* const* models, int32_t n_models, const d
       std::lock_guard<std::mutex> lk(g_scratch_mu);
       st = scratch_for(m0->device, &sc);
       if (st != RT_OK) return st;
+      if (sc->start_cap < size_t(npx)) {
+        dev_free(sc->start_idx, sc->start_cap * 6 * sizeof(double));
+        sc->start_idx = nullptr;
+        sc->start_cap = 0;
+        st = dev_alloc((void**)&sc->start_idx, size_t(npx) * 6 * sizeof(double), "launch table");
+        if (st != RT_OK) return st;
+        sc->start_cap = size_t(npx);
+      }
+      const size_t nne = size_t(npx) * size_t(n_models);
+      if (sc->start_ne_cap < nne) {
+        dev_free(sc->start_ne, sc->start_ne_cap * sizeof(float));
+        sc->start_ne = nullptr;
+        sc->start_ne_cap = 0;
+        st = dev_alloc((void**)&sc->start_ne, nne * sizeof(float), "start n_e table");
+        if (st != RT_OK) return st;
+        sc->start_ne_cap = nne;
+      }
       if (n_path_rays > 0 && sc->path_cap < size_t(n_path_rays)) {
         dev_free(sc->path_rays, sc->path_cap * sizeof(int32_t));
         sc->path_rays = nullptr;
@@ -405,7 +426,11 @@ rt_status rt_trace_maps(const rt_model* const* models, int32_t n_models, const d
     TraceArgs a{};
     a.g = m0->geom;
     for (int k = 0; k < n_models; ++k) a.models[k] = {models[k]->nfg, models[k]->te};
-    for (int k = 0; k < n_freq; ++k) a.freqs[k] = freq_hz[k];
+    for (int k = 0; k < n_freq; ++k) {
+      a.freqs[k] = freq_hz[k];
+      a.xf[k] = (8.98e3 / freq_hz[k]) * (8.98e3 / freq_hz[k]);
+      a.lnf[k] = float(std::log(freq_hz[k]));
+    }
     a.n_models = n_models;
     a.n_freq = n_freq;
     a.nu = I.nu; a.nv = I.nv;
@@ -441,6 +466,10 @@ rt_status rt_trace_maps(const rt_model* const* models, int32_t n_models, const d
       st = hip_check(launch_fill_u32(reinterpret_cast<unsigned*>(stats_out), 0u, sizeof(rt_trace_stats) / 4, s), "stats fill");
       if (st != RT_OK) return st;
     }
+    a.launch = sc->start_idx;
+    a.launch_ne = sc->start_ne;
+    st = hip_check(launch_start_index(a, sc->start_idx, sc->start_ne, s), "start index");
+    if (st != RT_OK) return st;
     const bool mixed = (P.flags & RT_PREC_ALL_FP32) == 0;
     if (P.flags & RT_SCHED_PLAIN) {
       const int waves = a.tiles_per_image;
@@ -458,6 +487,11 @@ rt_status rt_trace_maps(const rt_model* const* models, int32_t n_models, const d
         slot = sc->next_slot++ % kCounterSlots;
       }
       a.counters = sc->counters + size_t(slot) * kXcds;
+      a.refill_min_idle = 64;
+      if (const char* e = std::getenv("RT_REFILL_MIN_IDLE")) {
+        const int v = std::atoi(e);
+        if (v >= 1 && v <= 64) a.refill_min_idle = v;
+      }
       a.n_bands = kXcds;
       const int n_images = n_models * n_freq;
       a.range_lo[0] = 0;

@@ -35,6 +35,11 @@ struct TraceArgs {
   DevGeom g;
   DevModelPtrs models[kMaxModels];
   double freqs[kMaxFreqs];
+  double xf[kMaxFreqs];       // X / n_e = (8.98e3 / f)^2 per frequency
+  float lnf[kMaxFreqs];       // ln f per frequency
+  const double* launch;       // [nv * nu][6]: start point r0 and its continuous grid index
+                              // (missing pixels: their image-plane point, index0 = -1, index1 = b)
+  const float* launch_ne;     // [n_models][nv * nu]: n_e at each pixel's start point
   int n_models, n_freq;
   int nu, nv, tiles_u, tiles_v, tiles_per_image;
   int image0;                 // plain launches: flat (model * n_freq + freq) index of the image
@@ -56,6 +61,7 @@ struct TraceArgs {
   unsigned* counters;         // kXcds claim counters (zeroed before launch)
   int range_lo[kXcds + 1];
   int n_bands;                // image rows split into bands, one per range
+  int refill_min_idle;        // a wave refills once at least this many lanes are idle (1..64)
 };
 
 // Launchers (rt_kernels.hip).
@@ -64,6 +70,7 @@ hipError_t launch_pack(const DevGeom& g, const float* ne, const float* te, float
 hipError_t launch_validate(const float* ne, const float* te, long long n, int* bad, hipStream_t s);
 hipError_t launch_fill_u32(unsigned* p, unsigned val, long long n, hipStream_t s);
 hipError_t launch_trace(const TraceArgs& a, bool plain, bool mixed, int grid_blocks, hipStream_t s);
+hipError_t launch_start_index(const TraceArgs& a, double* out, float* ne_out, hipStream_t s);
 int persistent_blocks_per_cu(bool mixed, int kind);
 
 }  // namespace rt

@@ -63,6 +63,49 @@ __global__ void k_fill_u32(unsigned* p, unsigned v, long long n) {
     p[i] = v;
 }
 
+// Per-pixel launch table (shared by all frequencies and models of a call): the
+// start point on the r_max sphere and its grid index in FP64 with the library
+// functions, and n_e there for every model (for p0 = n(r0) (-o)).
+template <int KIND>
+__global__ __launch_bounds__(256) void k_launch_table(TraceArgs a, double* out, float* ne_out) {
+  __shared__ float4 lds_c[4][8][kWaveLanes];
+  __shared__ float lds_t[4][8][kWaveLanes];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int n = a.nu * a.nv;
+  for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < n; p += gridDim.x * blockDim.x) {
+    const int i = p / a.nu, j = p - (p / a.nu) * a.nu;
+    double pu, pv, b2, x0;
+    pixel_start(a, i, j, pu, pv, b2, x0);
+    double* L = out + size_t(p) * 6;
+    if (b2 >= a.g.r_max * a.g.r_max) {
+      L[0] = pu * a.u[0] + pv * a.v[0];
+      L[1] = pu * a.u[1] + pv * a.v[1];
+      L[2] = pu * a.u[2] + pv * a.v[2];
+      L[3] = -1.0; L[4] = sqrt(b2); L[5] = 0.0;
+      for (int m = 0; m < a.n_models; ++m) ne_out[size_t(m) * n + p] = 0.0f;
+      continue;
+    }
+    RayState R;
+    R.rx = x0 * a.o[0] + pu * a.u[0] + pv * a.v[0];
+    R.ry = x0 * a.o[1] + pu * a.u[1] + pv * a.v[1];
+    R.rz = x0 * a.o[2] + pu * a.u[2] + pv * a.v[2];
+    index_exact<KIND>(a.g, R.rx, R.ry, R.rz, R.b0, R.b1, R.b2);
+    if (!(R.b0 >= 0.0)) R.b0 = 0.0;  // on the sphere the radial index is the last one (>= 0)
+    L[0] = R.rx; L[1] = R.ry; L[2] = R.rz; L[3] = R.b0; L[4] = R.b1; L[5] = R.b2;
+    StepOrigin O;
+    make_origin<KIND>(R, O);
+    for (int m = 0; m < a.n_models; ++m) {
+      CellCache C;
+      C.key = -1;
+      C.c = &lds_c[wave][0][lane];
+      C.t = &lds_t[wave][0][lane];
+      float ne, t;
+      eval_value<KIND>(a.g, a.models[m].nfg, a.models[m].te, C, O, 0.f, 0.f, 0.f, ne, t);
+      ne_out[size_t(m) * n + p] = ne;
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Per-wave statistics.
 // ---------------------------------------------------------------------------
@@ -114,7 +157,7 @@ __device__ __forceinline__ int xcd_remap(int bid, int nblocks) {
 // One launch per (model, frequency) image: a wave traces one 8x8 pixel tile.
 // ---------------------------------------------------------------------------
 template <bool MIXED, int KIND>
-__global__ __launch_bounds__(256) void k_trace_plain(TraceArgs a) {
+__global__ __launch_bounds__(256, 2) void k_trace_plain(TraceArgs a) {
   __shared__ float4 lds_c[4][8][kWaveLanes];
   __shared__ float lds_t[4][8][kWaveLanes];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -124,17 +167,17 @@ __global__ __launch_bounds__(256) void k_trace_plain(TraceArgs a) {
   const int j = tx * kTile + (lane & 7), i = ty * kTile + (lane >> 3);
   LaneStats st{};
   if (i < a.nv && j < a.nu) {
-    const int id = a.image0 * (a.nu * a.nv) + i * a.nu + j;
     RayState R;
     CellCache C;
     C.key = -1;
     C.c = &lds_c[wave][0][lane];
     C.t = &lds_t[wave][0][lane];
-    if (init_ray<KIND>(a, id, R, C)) {
+    if (init_ray(a, a.image0, i * a.nu + j, R, C)) {
       int code;
       do {
         code = ray_step<MIXED, KIND>(a, R, C);
       } while (code == kRunning);
+      finish_ray(a, R);
       lane_stats_add(st, R.n, code);
     } else {
       lane_stats_add(st, 0, kMiss);
@@ -150,7 +193,7 @@ __global__ __launch_bounds__(256) void k_trace_plain(TraceArgs a) {
 // the following step, so lanes stay busy while rays of very different lengths
 // finish at different times.  The loop ends when every range is exhausted and no
 // lane holds a ray; each ray takes at most max_steps steps, so every wave ends.
-__device__ __forceinline__ int tile_slot_ray(const TraceArgs& a, int t, int slot) {
+__device__ __forceinline__ int tile_slot_ray(const TraceArgs& a, int t, int slot, int& img_out) {
   int x = 0;
   while (x < kXcds - 1 && t >= a.range_lo[x + 1]) ++x;
   const int local = t - a.range_lo[x];
@@ -162,12 +205,13 @@ __device__ __forceinline__ int tile_slot_ray(const TraceArgs& a, int t, int slot
   const int ty = row0 + rem / a.tiles_u;
   const int tx = rem - (rem / a.tiles_u) * a.tiles_u;
   const int i = ty * kTile + (slot >> 3), j = tx * kTile + (slot & 7);
+  img_out = img;
   if (i >= a.nv || j >= a.nu) return -1;
-  return img * (a.nu * a.nv) + i * a.nu + j;
+  return i * a.nu + j;
 }
 
 template <bool MIXED, int KIND>
-__global__ __launch_bounds__(256) void k_trace_persistent(TraceArgs a) {
+__global__ __launch_bounds__(256, 2) void k_trace_persistent(TraceArgs a) {
   __shared__ float4 lds_c[4][8][kWaveLanes];
   __shared__ float lds_t[4][8][kWaveLanes];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -180,10 +224,16 @@ __global__ __launch_bounds__(256) void k_trace_persistent(TraceArgs a) {
   C.key = -1;
   C.c = &lds_c[wave][0][lane];
   C.t = &lds_t[wave][0][lane];
-  LaneStats st{};
+  // statistics: per-lane step sum and maximum; rays per code counted by ballot
+  unsigned long long lane_steps = 0;
+  unsigned lane_max = 0;
+  unsigned code_cnt[6] = {0, 0, 0, 0, 0, 0};
   const unsigned all = (1u << kXcds) - 1u;
   for (;;) {
     unsigned long long idle = __ballot(!active);
+    // refill once enough lanes are idle (or none is busy): fewer, larger refills keep
+    // the lanes of a wave at similar depths along their rays
+    if (__popcll(idle) < a.refill_min_idle && idle != ~0ull) idle = 0ull;
     while (idle != 0ull && (pool_left > 0 || exhausted != all)) {
       if (pool_left == 0) {
         int t = -1;
@@ -203,25 +253,42 @@ __global__ __launch_bounds__(256) void k_trace_persistent(TraceArgs a) {
       }
       const int rank = __popcll(idle & ((1ull << lane) - 1ull));
       const int take = min(__popcll(idle), pool_left);
+      bool missed = false;
       if (!active && rank < take) {
-        const int id = tile_slot_ray(a, cur_tile, (64 - pool_left) + rank);
-        if (id >= 0) {
-          if (init_ray<KIND>(a, id, R, C)) active = true;
-          else lane_stats_add(st, 0, kMiss);
+        int img;
+        const int pix = tile_slot_ray(a, cur_tile, (64 - pool_left) + rank, img);
+        if (pix >= 0) {
+          if (init_ray(a, img, pix, R, C)) active = true;
+          else missed = true;
         }
       }
+      code_cnt[kMiss] += (unsigned)__popcll(__ballot(missed));
       pool_left -= take;
       idle = __ballot(!active);
     }
     if (__ballot(active) == 0ull) break;
+    int done = kRunning;
     if (active) {
       const int code = ray_step<MIXED, KIND>(a, R, C);
       if (code != kRunning) {
+        finish_ray(a, R);
         active = false;
-        lane_stats_add(st, R.n, code);
+        lane_steps += (unsigned long long)R.n;
+        lane_max = max(lane_max, (unsigned)R.n);
+        done = code;
       }
     }
+    if (__ballot(done != kRunning)) {
+#pragma unroll
+      for (int k = 1; k < 6; ++k)
+        if (k != kMiss) code_cnt[k] += (unsigned)__popcll(__ballot(done == k));
+    }
   }
+  LaneStats st{};
+  st.steps = lane_steps;
+  st.max_steps = lane_max;
+  if (lane == 0)
+    for (int k = 0; k < 6; ++k) st.count[k] = code_cnt[k];
   wave_stats_flush(st, a.stats);
 }
 
@@ -243,6 +310,15 @@ hipError_t launch_pack(const DevGeom& g, const float* ne, const float* te, float
 
 hipError_t launch_validate(const float* ne, const float* te, long long n, int* bad, hipStream_t s) {
   hipLaunchKernelGGL(k_validate, dim3(grid_for(n, 256)), dim3(256), 0, s, ne, te, n, bad);
+  return hipGetLastError();
+}
+
+hipError_t launch_start_index(const TraceArgs& a, double* out, float* ne_out, hipStream_t s) {
+  const long long n = (long long)a.nu * a.nv;
+  if (a.g.kind == RT_GRID_SPHERICAL_LOGR)
+    hipLaunchKernelGGL((k_launch_table<RT_GRID_SPHERICAL_LOGR>), dim3(grid_for(n, 256)), dim3(256), 0, s, a, out, ne_out);
+  else
+    hipLaunchKernelGGL((k_launch_table<RT_GRID_CARTESIAN>), dim3(grid_for(n, 256)), dim3(256), 0, s, a, out, ne_out);
   return hipGetLastError();
 }
 

@@ -6,30 +6,145 @@
 //   dp/dt = -1/2 grad X with X = (8.98e3)^2 n_e / f^2 (|p| = n, ds = n dt).
 //   Perturbation retracing and magnification: Eqs. 5-11 (area without the 1/2).
 //   Transfer with the geometric term: Eqs. 2-3, 12; one exact exponential
-//   update per segment, composited front to back (same products as the
+//   update per segment, composited front to back (the same products as the
 //   back-to-front solution of Sec. 3.2).
 //   Free-free: Rayleigh-Jeans closed form with the two-branch Coulomb
 //   logarithm of Dulk (1985).
+//
+// Precision: every evaluation of the model (position offsets, coordinates,
+// trilinear gathers, forces) is FP32.  The ray state r_i, p_i and the grid index
+// of r_i accumulate in FP64; the ray-tube area and the optical depth / brightness
+// accumulators are FP64 (FP32 in the all-FP32 variant).
 #pragma once
 
 #include "rt_internal.hpp"
 
 namespace rt {
 
-constexpr float kTwoPiF = 6.28318530717958647692f;
 constexpr double kRsunCm = 6.957e10;
 constexpr float kFFCoefF = 9.78e-3f;
+constexpr float kPiF = 3.14159265358979323846f;
 
 enum : int { kRunning = 0, kExit = 1, kHit = 2, kMiss = 3, kMaxSteps = 4, kNonfinite = 5 };
 
 template <bool MIXED> struct RealOf { using T = double; };
 template <> struct RealOf<false> { using T = float; };
 
-// The 8 corners of the last cell a lane touched, kept in LDS: (n_e, index-space
-// gradient) and T of corner k = 4 i + 2 j + k' for offsets (i, j, k') along axes
-// 0, 1, 2.  Slots are corner-major ([corner][lane]) so that the 64 lanes of a
-// wave read consecutive 16-byte words (no bank conflicts).  Each lane only reads
-// its own slots, which it wrote itself; LDS operations of a wave complete in order.
+// ---------------------------------------------------------------------------
+// Small math kernels with few constants (so that nothing large is kept live
+// across the step loop).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float rcpf(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// Odd Taylor series of atan on |t| <= tan(pi/8): truncation below 2e-8.
+__device__ __forceinline__ float atan_poly(float t) {
+  const float t2 = t * t;
+  float s = 1.0f / 15.0f;
+  s = fmaf(s, -t2, 1.0f / 13.0f);
+  s = fmaf(s, -t2, 1.0f / 11.0f);
+  s = fmaf(s, -t2, 1.0f / 9.0f);
+  s = fmaf(s, -t2, 1.0f / 7.0f);
+  s = fmaf(s, -t2, 1.0f / 5.0f);
+  s = fmaf(s, -t2, 1.0f / 3.0f);
+  s = fmaf(s, -t2, 1.0f);
+  return t * s;
+}
+
+// atan2 in FP32: octant reduction to [0, 1], then atan(a) = pi/4 + atan((a-1)/(a+1))
+// above tan(pi/8), then the series.  Absolute error below 3e-8 rad.
+__device__ __forceinline__ float fast_atan2f(float y, float x) {
+  const float ax = fabsf(x), ay = fabsf(y);
+  const float mx = fmaxf(ax, ay), mn = fminf(ax, ay);
+  const float q = mx > 0.0f ? mn * rcpf(mx) : 0.0f;
+  const bool red = q > 0.41421356f;
+  const float t = red ? (q - 1.0f) * rcpf(q + 1.0f) : q;
+  float r = atan_poly(t) + (red ? 0.25f * kPiF : 0.0f);
+  if (ay > ax) r = 0.5f * kPiF - r;
+  if (x < 0.0f) r = kPiF - r;
+  return copysignf(r, y);
+}
+
+// log1p in FP32: 2 atanh(z / (2 + z)) by its odd series for |z| <= 1/4
+// (relative truncation below 1e-10); log2 instruction otherwise.
+__device__ __forceinline__ float fast_log1pf(float z) {
+  if (fabsf(z) <= 0.25f) {
+    const float w = z * rcpf(2.0f + z);
+    const float w2 = w * w;
+    float s = 1.0f / 9.0f;
+    s = fmaf(s, w2, 1.0f / 7.0f);
+    s = fmaf(s, w2, 1.0f / 5.0f);
+    s = fmaf(s, w2, 1.0f / 3.0f);
+    s = fmaf(s, w2, 1.0f);
+    return 2.0f * w * s;
+  }
+  return __builtin_amdgcn_logf(1.0f + z) * 0.69314718056f;
+}
+
+// FP64 reciprocal: hardware estimate and two Newton steps.
+__device__ __forceinline__ double rcp64(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  y = fma(y, fma(-x, y, 1.0), y);
+  y = fma(y, fma(-x, y, 1.0), y);
+  return y;
+}
+
+// FP64 series for the per-step index increments, valid for small arguments
+// only (|w|, |t| <= 1/32): three shared coefficients keep the loop free of
+// FP64 constants that the compiler would pin in registers.
+// log1p(z) = 2 atanh(w), w = z / (2 + z): truncation w^9/9 < 4e-15 relative.
+__device__ __forceinline__ double log1p_small64(double z) {
+  const double w = z * rcp64(2.0 + z);
+  const double w2 = w * w;
+  const double s = fma(fma(fma(1.0 / 7.0, w2, 1.0 / 5.0), w2, 1.0 / 3.0), w2, 1.0);
+  return 2.0 * w * s;
+}
+// atan(t) = t (1 - t^2/3 + t^4/5 - t^6/7): truncation t^8/9 < 1e-13 relative.
+__device__ __forceinline__ double atan_small64(double t) {
+  const double t2 = t * t;
+  const double s = fma(fma(fma(-1.0 / 7.0, t2, 1.0 / 5.0), t2, -1.0 / 3.0), t2, 1.0);
+  return t * s;
+}
+constexpr double kSmall64 = 1.0 / 32.0;
+
+// General FP64 atan2 and log for the rare large increments, built on the same
+// series: atan(t) = 2 atan(t / (1 + sqrt(1 + t^2))) halves the argument until
+// |t| <= 1/32, log(x) = 2 log(sqrt(x)) until |x - 1| <= 1/32.
+__device__ __forceinline__ double atan2_64(double y, double x) {
+  if (x == 0.0 && y == 0.0) return 0.0;
+  const bool flip = x < 0.0;
+  const double ax = flip ? -x : x;
+  double t = fabs(y) > ax * 1e12 ? 1e12 : y * rcp64(ax);
+  double scale = 1.0;
+  while (fabs(t) > kSmall64) {
+    t = t * rcp64(1.0 + sqrt(fma(t, t, 1.0)));
+    scale *= 2.0;
+  }
+  double r = scale * atan_small64(t);  // in (-pi/2, pi/2)
+  if (flip) r = (y >= 0.0 ? 3.141592653589793238463 : -3.141592653589793238463) - r;
+  return r;
+}
+__device__ __forceinline__ double log_64(double x) {
+  double scale = 1.0;
+  while (fabs(x - 1.0) > kSmall64) {
+    x = sqrt(x);
+    scale *= 2.0;
+  }
+  return scale * log1p_small64(x - 1.0);
+}
+
+// Library FP64 functions, kept out of line: used at ray start and when an
+// incremental index update leaves its series range (rare).
+__device__ __noinline__ double lib_log(double x) { return log(x); }
+__device__ __noinline__ double lib_atan2(double y, double x) { return atan2(y, x); }
+
+// ---------------------------------------------------------------------------
+// Per-lane cell cache in LDS: the 8 corners of the last cell a lane touched,
+// (n_e, index-space gradient) and T of corner k = 4 i + 2 j + k' for offsets
+// (i, j, k') along axes 0, 1, 2.  Slots are corner-major ([corner][lane]) so
+// that the 64 lanes of a wave read consecutive 16-byte words (no bank
+// conflicts).  Each lane only reads its own slots, which it wrote itself; LDS
+// operations of a wave complete in order.
+// ---------------------------------------------------------------------------
 constexpr int kWaveLanes = 64;
 struct CellCache {
   int key;
@@ -37,128 +152,129 @@ struct CellCache {
   float* t;   // LDS, corner k at t[k * kWaveLanes]
 };
 
-// Grid coordinates of a step's origin r_i, computed once per step in FP64 from
-// the compensated position.  Every evaluation point of the step is r_i + d
-// with a small FP32 offset d; its continuous grid index is the origin's FP64
-// index plus an FP32 increment from cancellation-free small-offset formulas.
-// FP32 alone cannot place a point inside a cell to better than
-// ulp(r)/(r dl) ~ 1e-6..5e-6 of a cell, which would perturb every force by
-// ~1e-6 and move exit points by ~1e-4 R_sun after a strongly refracted path.
-struct StepOrigin {
-  float x, y, z;        // r_i rounded to FP32 (for the offset formulas)
-  float r2, rho2, rho;  // |r_i|^2, rho_i^2, rho_i
-  double b0, b1, b2;    // continuous grid index of r_i
-};
+__device__ __forceinline__ void ensure_cell(const DevGeom& g, const float4* nfg, const float* te, CellCache& C,
+                                            int key) {
+  if (key == C.key) return;
+  C.key = key;
+  const int s1 = g.n2p, s0 = g.n1 * g.n2p;
+  const int off[4] = {0, s1, s0, s0 + s1};
+  // two corners (one 32-byte run along axis 2) at a time keeps few values live
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const float4 a0 = nfg[key + off[k]], a1 = nfg[key + off[k] + 1];
+    const float t0 = te[key + off[k]], t1 = te[key + off[k] + 1];
+    C.c[(2 * k) * kWaveLanes] = a0;
+    C.c[(2 * k + 1) * kWaveLanes] = a1;
+    C.t[(2 * k) * kWaveLanes] = t0;
+    C.t[(2 * k + 1) * kWaveLanes] = t1;
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
 
+// ---------------------------------------------------------------------------
+// Grid index bookkeeping.  The continuous grid index of a step's origin r_i is
+// carried in FP64 and advanced incrementally with cancellation-free small-offset
+// formulas; every evaluation point r_i + d (d a small FP32 offset) then gets its
+// index as the origin's (integer, FP32 fraction) plus an FP32 increment.  FP32
+// alone cannot place a point inside a cell to better than ulp(r)/(r dl), about
+// 1e-6..5e-6 of a cell, which perturbs every force by ~1e-6 and moves the exit
+// point of a strongly refracted ray by ~1e-4 R_sun.
+// ---------------------------------------------------------------------------
 template <int KIND>
-__device__ __forceinline__ void make_origin(const DevGeom& g, double X, double Y, double Z, StepOrigin& O) {
-  O.x = float(X); O.y = float(Y); O.z = float(Z);
+__device__ __forceinline__ void index_exact(const DevGeom& g, double X, double Y, double Z, double& b0, double& b1,
+                                            double& b2) {
   if constexpr (KIND == RT_GRID_SPHERICAL_LOGR) {
     const double rho2 = X * X + Y * Y;
     const double r2 = rho2 + Z * Z;
-    const double rho = sqrt(rho2);
-    O.r2 = float(r2); O.rho2 = float(rho2); O.rho = float(rho);
-    O.b0 = (0.5 * log(r2) - double(g.ln_rin_d)) * g.inv_dl_d;
-    O.b1 = atan2(rho, Z) * g.inv_dth_d - 0.5;
-    double ph = (rho2 > 0.0) ? atan2(Y, X) : 0.0;
+    b0 = (0.5 * lib_log(r2) - g.ln_rin_d) * g.inv_dl_d;
+    b1 = lib_atan2(sqrt(rho2), Z) * g.inv_dth_d - 0.5;
+    double ph = rho2 > 0.0 ? lib_atan2(Y, X) : 0.0;
     if (ph < 0.0) ph += 6.283185307179586476925;
-    O.b2 = ph * g.inv_dph_d;
+    b2 = ph * g.inv_dph_d;
+    if (b2 >= double(g.n2)) b2 -= double(g.n2);
   } else {
-    O.r2 = 0.f; O.rho2 = 0.f; O.rho = 0.f;
-    O.b0 = (X - double(g.org_d[0])) * g.inv_sp_d[0];
-    O.b1 = (Y - double(g.org_d[1])) * g.inv_sp_d[1];
-    O.b2 = (Z - double(g.org_d[2])) * g.inv_sp_d[2];
+    b0 = (X - g.org_d[0]) * g.inv_sp_d[0];
+    b1 = (Y - g.org_d[1]) * g.inv_sp_d[1];
+    b2 = (Z - g.org_d[2]) * g.inv_sp_d[2];
   }
+}
+
+struct StepOrigin {
+  float x, y, z;        // r_i in FP32 (for the offset formulas)
+  float r2, inv_r2, rho2, rho;
+  int i0, i1, i2;       // integer part of r_i's grid index
+  float f0, f1, f2;     // fractional part in [0, 1)
+};
+
+__device__ __forceinline__ void split_index(double b, int& i, float& f) {
+  double fl = floor(b);
+  if (!(fl >= -1.0e9 && fl <= 1.0e9)) fl = 0.0;  // NaN guard
+  i = int(fl);
+  f = float(b - fl);
 }
 
 struct Loc {
   int key;
   float u, v, w;
-  bool clamp0, clamp1, clamp2;
-  // spherical chain-rule pieces at the evaluation point
-  float rinv, rho, rhoinv, x, y, z;
+  // chain-rule pieces at the evaluation point (spherical)
+  float rinv, rhoinv, rho, x, y, z;
   bool axis;
 };
 
-// Clamp a continuous index to [0, n-1] (NaN -> 0); report whether it was outside.
-__device__ __forceinline__ double clamp_index(double xi, int n, bool& clamped) {
-  clamped = false;
-  if (!(xi >= 0.0)) { clamped = true; return 0.0; }
-  const double hi = double(n - 1);
-  if (xi > hi) { clamped = true; return hi; }
-  return xi;
+// Cell of a clamped axis from (integer base, FP32 index offset): a in [0, n-2],
+// u in [0, 1]; beyond an edge the index is held at the edge.
+__device__ __forceinline__ void cell_clamped(float x, int I, int n, int& a, float& u) {
+  float fk = floorf(x);
+  if (!(fk >= -1.0e9f && fk <= 1.0e9f)) fk = 0.0f;  // NaN guard keeps every gather in bounds
+  u = x - fk;
+  a = I + int(fk);
+  if (a < 0) { a = 0; u = 0.0f; }
+  else if (a > n - 2) { a = n - 2; u = 1.0f; }
+}
+
+__device__ __forceinline__ void cell_periodic(float x, int I, int n, int& c, float& w) {
+  float fk = floorf(x);
+  if (!(fk >= -1.0e9f && fk <= 1.0e9f)) fk = 0.0f;
+  w = x - fk;
+  c = I + int(fk);
+  c = c % n;
+  if (c < 0) c += n;
 }
 
 template <int KIND>
 __device__ __forceinline__ void locate(const DevGeom& g, const StepOrigin& O, float dx, float dy, float dz, Loc& L) {
-  double x0, x1, x2;
+  float x0, x1, x2;
   if constexpr (KIND == RT_GRID_SPHERICAL_LOGR) {
     // radius: |q|^2 = |r_i|^2 (1 + c / |r_i|^2), c = 2 r_i.d + |d|^2
     const float rd = O.x * dx + O.y * dy;
-    const float c = 2.0f * (rd + O.z * dz) + (dx * dx + dy * dy + dz * dz);
-    const float lr = log1pf(c / O.r2);
-    x0 = O.b0 + double(0.5f * lr * g.inv_dl);
+    const float dd = dx * dx + dy * dy;
+    const float c = 2.0f * (rd + O.z * dz) + (dd + dz * dz);
+    x0 = O.f0 + 0.5f * fast_log1pf(c * O.inv_r2) * g.inv_dl;
     // azimuth: angle from (x_i, y_i) to (x_i + dx, y_i + dy)
-    const float dphi = atan2f(O.x * dy - O.y * dx, O.rho2 + O.x * dx + O.y * dy);
-    x2 = O.b2 + double(dphi * g.inv_dph);
+    x2 = O.f2 + fast_atan2f(O.x * dy - O.y * dx, O.rho2 + rd) * g.inv_dph;
     // colatitude: angle from (z_i, rho_i) to (z_q, rho_q) in the meridional plane
-    const float e = 2.0f * rd + (dx * dx + dy * dy);
-    const float rho2q = fmaxf(O.rho2 + e, 0.0f);
-    const float rhoq = sqrtf(rho2q);
-    const float den_r = rhoq + O.rho;
-    const float drho = den_r > 0.0f ? e / den_r : 0.0f;
+    const float e = 2.0f * rd + dd;
+    const float rhoq = sqrtf(fmaxf(O.rho2 + e, 0.0f));
+    const float den = rhoq + O.rho;
+    const float drho = den > 0.0f ? e * rcpf(den) : 0.0f;
     const float zq = O.z + dz;
-    const float dth = atan2f(O.z * drho - O.rho * dz, O.z * zq + O.rho * rhoq);
-    x1 = O.b1 + double(dth * g.inv_dth);
-    const float r2q = O.r2 + c;
-    L.rinv = rsqrtf(r2q);
+    x1 = O.f1 + fast_atan2f(O.z * drho - O.rho * dz, O.z * zq + O.rho * rhoq) * g.inv_dth;
+    L.rinv = rsqrtf(O.r2 + c);
     L.rho = rhoq;
     L.axis = rhoq < 1e-12f;
-    L.rhoinv = L.axis ? 0.0f : 1.0f / rhoq;
+    L.rhoinv = L.axis ? 0.0f : rcpf(rhoq);
     L.x = O.x + dx; L.y = O.y + dy; L.z = zq;
   } else {
-    x0 = O.b0 + double(dx * g.inv_sp[0]);
-    x1 = O.b1 + double(dy * g.inv_sp[1]);
-    x2 = O.b2 + double(dz * g.inv_sp[2]);
+    x0 = O.f0 + dx * g.inv_sp[0];
+    x1 = O.f1 + dy * g.inv_sp[1];
+    x2 = O.f2 + dz * g.inv_sp[2];
   }
-  bool c0, c1, c2 = false;
-  const double xr = clamp_index(x0, g.n0, c0);
-  const double xt = clamp_index(x1, g.n1, c1);
-  const int a = min(int(floor(xr)), g.n0 - 2);
-  const int b = min(int(floor(xt)), g.n1 - 2);
-  int c;
-  double xp;
-  if constexpr (KIND == RT_GRID_SPHERICAL_LOGR) {
-    // periodic phi: wrap into [0, n2)
-    xp = x2;
-    if (!(xp >= 0.0 && xp < 4.0 * g.n2)) xp = (xp >= -4.0 * g.n2) ? xp + 4.0 * g.n2 : 0.0;  // NaN / far guard
-    const double fl = floor(xp);
-    c = int(fl);
-    c %= g.n2;
-    L.w = float(xp - fl);
-  } else {
-    xp = clamp_index(x2, g.n2, c2);
-    c = min(int(floor(xp)), g.n2 - 2);
-    L.w = float(xp - double(c));
-  }
+  int a, b, c;
+  cell_clamped(x0, O.i0, g.n0, a, L.u);
+  cell_clamped(x1, O.i1, g.n1, b, L.v);
+  if constexpr (KIND == RT_GRID_SPHERICAL_LOGR) cell_periodic(x2, O.i2, g.n2, c, L.w);
+  else cell_clamped(x2, O.i2, g.n2, c, L.w);
   L.key = (a * g.n1 + b) * g.n2p + c;
-  L.u = float(xr - double(a));
-  L.v = float(xt - double(b));
-  L.clamp0 = c0; L.clamp1 = c1; L.clamp2 = c2;
-}
-
-__device__ __forceinline__ void ensure_cell(const DevGeom& g, const DevModelPtrs& m, CellCache& C, int key) {
-  if (key == C.key) return;
-  C.key = key;
-  const int s1 = g.n2p, s0 = g.n1 * g.n2p;
-  const float4* p = m.nfg + key;
-  const float* t = m.te + key;
-  const int off[8] = {0, 1, s1, s1 + 1, s0, s0 + 1, s0 + s1, s0 + s1 + 1};
-#pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    C.c[k * kWaveLanes] = p[off[k]];
-    C.t[k * kWaveLanes] = t[off[k]];
-  }
 }
 
 __device__ __forceinline__ void weights8(float u, float v, float w, float W[8]) {
@@ -168,35 +284,37 @@ __device__ __forceinline__ void weights8(float u, float v, float w, float W[8]) 
   W[4] = a10 * w0; W[5] = a10 * w; W[6] = a11 * w0; W[7] = a11 * w;
 }
 
-// n_e and grad n_e [cm^-3 / R_sun] at a point.
+// n_e and grad n_e [cm^-3 / R_sun] at r_i + d.  The gradient is the trilinear
+// interpolant of the per-vertex index-space gradient (continuous across cell
+// faces and clamped edges), mapped to Cartesian with the spherical unit vectors.
 template <int KIND>
-__device__ __forceinline__ void eval_grad(const DevGeom& g, const DevModelPtrs& m, CellCache& C, const StepOrigin& O,
-                                          float dx, float dy, float dz, float& ne, float& gx, float& gy, float& gz) {
+__device__ __forceinline__ void eval_grad(const DevGeom& g, const float4* nfg, const float* te, CellCache& C,
+                                          const StepOrigin& O, float dx, float dy, float dz, float& ne, float& gx,
+                                          float& gy, float& gz) {
   Loc L;
   locate<KIND>(g, O, dx, dy, dz, L);
-  ensure_cell(g, m, C, L.key);
+  ensure_cell(g, nfg, te, C, L.key);
   float W[8];
   weights8(L.u, L.v, L.w, W);
   float n = 0.f, G0 = 0.f, G1 = 0.f, G2 = 0.f;
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
     const float4 q = C.c[k * kWaveLanes];
-    n += W[k] * q.x;
-    G0 += W[k] * q.y;
-    G1 += W[k] * q.z;
-    G2 += W[k] * q.w;
+    n = fmaf(W[k], q.x, n);
+    G0 = fmaf(W[k], q.y, G0);
+    G1 = fmaf(W[k], q.z, G1);
+    G2 = fmaf(W[k], q.w, G2);
+    if (k == 3) __builtin_amdgcn_sched_barrier(0);
   }
-  // Clamped edges keep the edge vertex's gradient: the force is continuous there.
   ne = n;
   if constexpr (KIND == RT_GRID_SPHERICAL_LOGR) {
     // grad = G0/(r dl) r_hat + G1/(r dth) theta_hat + G2/(r sin(theta) dphi) phi_hat
-    const float gr = G0 * g.inv_dl * L.rinv;
     const float gt = G1 * g.inv_dth * L.rinv;
     const float ct = L.z * L.rinv, st = L.rho * L.rinv;
     const float cph = L.axis ? 1.0f : L.x * L.rhoinv;
     const float sph = L.axis ? 0.0f : L.y * L.rhoinv;
     const float gp = L.axis ? 0.0f : G2 * g.inv_dph * L.rhoinv;
-    const float grr = gr * L.rinv;
+    const float grr = G0 * g.inv_dl * L.rinv * L.rinv;
     gx = grr * L.x + gt * ct * cph - gp * sph;
     gy = grr * L.y + gt * ct * sph + gp * cph;
     gz = grr * L.z - gt * st;
@@ -207,39 +325,43 @@ __device__ __forceinline__ void eval_grad(const DevGeom& g, const DevModelPtrs& 
   }
 }
 
-// n_e and T at a point (values only).
+// n_e and T at r_i + d (values only).
 template <int KIND>
-__device__ __forceinline__ void eval_value(const DevGeom& g, const DevModelPtrs& m, CellCache& C, const StepOrigin& O,
-                                           float dx, float dy, float dz, float& ne, float& te) {
+__device__ __forceinline__ void eval_value(const DevGeom& g, const float4* nfg, const float* te, CellCache& C,
+                                           const StepOrigin& O, float dx, float dy, float dz, float& ne, float& t) {
   Loc L;
   locate<KIND>(g, O, dx, dy, dz, L);
-  ensure_cell(g, m, C, L.key);
+  ensure_cell(g, nfg, te, C, L.key);
   float W[8];
   weights8(L.u, L.v, L.w, W);
-  float n = 0.f, t = 0.f;
+  float n = 0.f, tt = 0.f;
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
-    n += W[k] * C.c[k * kWaveLanes].x;
-    t += W[k] * C.t[k * kWaveLanes];
+    n = fmaf(W[k], C.c[k * kWaveLanes].x, n);
+    tt = fmaf(W[k], C.t[k * kWaveLanes], tt);
   }
   ne = n;
-  te = t;
+  t = tt;
 }
 
+// ---------------------------------------------------------------------------
+// Ray state and its life cycle.
+// ---------------------------------------------------------------------------
 struct RayState {
-  double rx, ry, rz;                 // position r_i (FP64 accumulator)
-  double px, py, pz;                 // normalised wavevector p_i (FP64 accumulator)
-  double A, P;                       // composite: emitted part, transmittance (front to back)
+  double rx, ry, rz;        // position r_i (on termination: the end point)
+  double px, py, pz;        // normalised wavevector p_i
+  double b0, b1, b2;        // continuous grid index of r_i
+  double A;                 // composite: emitted part (front to back)
+  double lam_tot;           // optical depth of the segments so far, geometric term included
   double tau, lns, s_arc;
-  float rmin;
-  int n;                             // steps taken
-  int id;                            // flat ray index
-  int model;
-  float cf;                          // -1/2 Xf, Xf = (8.98e3 / f)^2
-  double cfd;                        // the same in FP64 (applied to the accumulated increments)
-  float xff;                         // Xf
-  float f2, lnf;                     // f^2, ln f
-  double f;
+  double cfd;               // -1/2 Xf in FP64, Xf = (8.98e3 / f)^2
+  const float4* nfg;        // this ray's model
+  const float* te;
+  float rmin, lam_end;
+  float cf, xff, f2, lnf;
+  int n;                    // steps taken
+  int id;                   // flat ray index
+  int code;
   int path_slot, path_len;
 };
 
@@ -295,90 +417,162 @@ __device__ __forceinline__ void write_miss(const TraceArgs& a, int id, double b,
   }
 }
 
-// Launch (Sec. 3.2): start on the r_max sphere, direction -o, p0 = n(r0) (-o).
-// Returns false for a ray that misses the model (output written).
 template <int KIND>
-__device__ bool init_ray(const TraceArgs& a, int id, RayState& R, CellCache& C) {
-  int model, fi, i, j;
-  ray_coords(a, id, model, fi, i, j);
-  const double pu = -a.half_u + (j + 0.5) * 2.0 * a.half_u / a.nu;
-  const double pv = -a.half_v + (i + 0.5) * 2.0 * a.half_v / a.nv;
-  const double b2 = pu * pu + pv * pv;
+__device__ __forceinline__ void make_origin(const RayState& R, StepOrigin& O) {
+  const double rho2 = R.rx * R.rx + R.ry * R.ry;
+  const double r2 = rho2 + R.rz * R.rz;
+  double rho;
+  O.x = float(R.rx); O.y = float(R.ry); O.z = float(R.rz);
+  if constexpr (KIND == RT_GRID_SPHERICAL_LOGR) {
+    rho = sqrt(rho2);
+    O.r2 = float(r2); O.inv_r2 = float(rcp64(r2)); O.rho2 = float(rho2); O.rho = float(rho);
+  } else {
+    rho = 0.0;
+    O.r2 = 0.f; O.inv_r2 = 0.f; O.rho2 = 0.f; O.rho = 0.f;
+  }
+  split_index(R.b0, O.i0, O.f0);
+  split_index(R.b1, O.i1, O.f1);
+  split_index(R.b2, O.i2, O.f2);
+}
+
+// Advance the origin's grid index by the step increment d (FP64 small-offset
+// formulas; exact recomputation outside their range).
+template <int KIND>
+__device__ __forceinline__ void index_advance(const DevGeom& g, RayState& R, double dx, double dy, double dz) {
+  if constexpr (KIND == RT_GRID_SPHERICAL_LOGR) {
+    const double X = R.rx, Y = R.ry, Z = R.rz;  // old origin
+    const double rho2 = X * X + Y * Y, r2 = rho2 + Z * Z, rho = sqrt(rho2);
+    const double rd = X * dx + Y * dy;
+    const double dd = dx * dx + dy * dy;
+    const double c = 2.0 * (rd + Z * dz) + (dd + dz * dz);
+    const double z = c * rcp64(r2);
+    const double nX = X + dx, nY = Y + dy, nZ = Z + dz;
+    if (fabs(z) <= kSmall64) R.b0 += 0.5 * log1p_small64(z) * g.inv_dl_d;
+    else R.b0 = (0.5 * log_64(nX * nX + nY * nY + nZ * nZ) - g.ln_rin_d) * g.inv_dl_d;
+    // azimuth
+    const double num = X * dy - Y * dx, den = rho2 + rd;
+    if (den > 0.0 && fabs(num) <= kSmall64 * den) {
+      R.b2 += atan_small64(num * rcp64(den)) * g.inv_dph_d;
+    } else {
+      double ph = (nX * nX + nY * nY) > 0.0 ? atan2_64(nY, nX) : 0.0;
+      if (ph < 0.0) ph += 6.283185307179586476925;
+      R.b2 = ph * g.inv_dph_d;
+    }
+    if (R.b2 < 0.0) R.b2 += double(g.n2);
+    if (R.b2 >= double(g.n2)) R.b2 -= double(g.n2);
+    // colatitude
+    const double e = 2.0 * rd + dd;
+    const double rhoq = sqrt(fmax(rho2 + e, 0.0));
+    const double dsum = rhoq + rho;
+    const double drho = dsum > 0.0 ? e * rcp64(dsum) : 0.0;
+    const double numt = Z * drho - rho * dz, dent = Z * nZ + rho * rhoq;
+    if (dent > 0.0 && fabs(numt) <= kSmall64 * dent) R.b1 += atan_small64(numt * rcp64(dent)) * g.inv_dth_d;
+    else R.b1 = atan2_64(rhoq, nZ) * g.inv_dth_d - 0.5;
+  } else {
+    R.b0 += dx * g.inv_sp_d[0];
+    R.b1 += dy * g.inv_sp_d[1];
+    R.b2 += dz * g.inv_sp_d[2];
+  }
+}
+
+// Launch (Sec. 3.2): pixel centre (pu, pv) on the image plane; the ray starts on
+// the r_max sphere and travels along -o.
+__device__ __forceinline__ void pixel_start(const TraceArgs& a, int i, int j, double& pu, double& pv, double& b2,
+                                            double& x0) {
+  pu = -a.half_u + (j + 0.5) * 2.0 * a.half_u / a.nu;
+  pv = -a.half_v + (i + 0.5) * 2.0 * a.half_v / a.nv;
+  b2 = pu * pu + pv * pv;
   const double rmax = a.g.r_max;
-  if (b2 >= rmax * rmax) {
-    write_miss(a, id, sqrt(b2), pu * a.u[0] + pv * a.v[0], pu * a.u[1] + pv * a.v[1], pu * a.u[2] + pv * a.v[2]);
+  x0 = (b2 < rmax * rmax) ? sqrt(rmax * rmax - b2) : 0.0;
+}
+
+// Start ray `pix` (flat pixel index) of image `img` (= model * n_freq + freq):
+// r0 and its grid index come from the per-pixel table, p0 = n(r0) (-o).
+// Returns false for a ray that misses the model (its output is written).
+__device__ __forceinline__ bool init_ray(const TraceArgs& a, int img, int pix, RayState& R, CellCache& C) {
+  const int npx = a.nu * a.nv;
+  const int model = img / a.n_freq;
+  const int fi = img - model * a.n_freq;
+  const int id = img * npx + pix;
+  const double* L = a.launch + size_t(pix) * 6;
+  R.rx = L[0]; R.ry = L[1]; R.rz = L[2];
+  R.b0 = L[3]; R.b1 = L[4]; R.b2 = L[5];
+  if (R.b0 < 0.0) {  // missing pixel: (rx, ry, rz) is its image-plane point, b1 its impact parameter
+    write_miss(a, id, R.b1, R.rx, R.ry, R.rz);
     return false;
   }
-  const double x0 = sqrt(rmax * rmax - b2);
-  const double r0x = x0 * a.o[0] + pu * a.u[0] + pv * a.v[0];
-  const double r0y = x0 * a.o[1] + pu * a.u[1] + pv * a.v[1];
-  const double r0z = x0 * a.o[2] + pu * a.u[2] + pv * a.v[2];
-  R.rx = r0x; R.ry = r0y; R.rz = r0z;
   C.key = -1;  // the lane's cached cell may belong to another model
-  const double f = a.freqs[fi];
-  const double xf = (8.98e3 / f) * (8.98e3 / f);
-  R.f = f;
+  const double xf = a.xf[fi];
   R.xff = float(xf);
   R.cf = float(-0.5 * xf);
   R.cfd = -0.5 * xf;
-  R.f2 = float(f * f);
-  R.lnf = float(log(f));
-  R.model = model;
+  R.f2 = float(a.freqs[fi] * a.freqs[fi]);
+  R.lnf = a.lnf[fi];
+  R.nfg = a.models[model].nfg;
+  R.te = a.models[model].te;
   R.id = id;
   double nidx = 1.0;
   if (a.flags & RT_USE_REFRACTION) {
-    float ne, te;
-    StepOrigin O;
-    make_origin<KIND>(a.g, r0x, r0y, r0z, O);
-    eval_value<KIND>(a.g, a.models[model], C, O, 0.f, 0.f, 0.f, ne, te);
-    const float n2 = 1.0f - R.xff * ne;
+    const float n2 = 1.0f - R.xff * a.launch_ne[size_t(model) * npx + pix];
     nidx = n2 > 0.f ? double(sqrtf(n2)) : 0.0;
   }
   R.px = -nidx * a.o[0]; R.py = -nidx * a.o[1]; R.pz = -nidx * a.o[2];
-  R.A = 0.0; R.P = 1.0; R.tau = 0.0; R.lns = 0.0; R.s_arc = 0.0;
-  R.rmin = float(rmax);
+  R.A = 0.0; R.lam_tot = 0.0; R.tau = 0.0; R.lns = 0.0; R.s_arc = 0.0;
+  R.rmin = float(a.g.r_max);
+  R.lam_end = 1.0f;
   R.n = 0;
+  R.code = kRunning;
   R.path_slot = (a.n_path > 0) ? find_path_slot(a, id) : -1;
   R.path_len = 0;
   return true;
 }
 
-template <class Real>
-__device__ __forceinline__ void finish_ray(const TraceArgs& a, const RayState& R, int code, Real ex, Real ey, Real ez,
-                                           Real lam) {
-  const double tbc = (code == kHit) ? a.tb_inner : a.tb_sky;
-  const double tb = R.A + R.P * tbc;
-  a.tb[R.id] = float(tb);
+__device__ __forceinline__ void finish_ray(const TraceArgs& a, const RayState& R) {
+  const double tbc = (R.code == kHit) ? a.tb_inner : a.tb_sky;
+  const float trans = __builtin_amdgcn_exp2f(-1.44269504089f * float(R.lam_tot));
+  a.tb[R.id] = float(R.A + double(trans) * tbc);
   if (a.info) {
     rt_ray_info inf;
     inf.n_steps = R.n;
-    inf.code = int8_t(code);
-    inf.flags = ((code == kExit || code == kHit) && (lam < Real(1e-4) || lam > Real(1) - Real(1e-4)))
+    inf.code = int8_t(R.code);
+    inf.flags = ((R.code == kExit || R.code == kHit) && (R.lam_end < 1e-4f || R.lam_end > 1.0f - 1e-4f))
                     ? int8_t(RT_RAY_FLAG_MARGINAL) : int8_t(0);
     inf._pad[0] = inf._pad[1] = 0;
-    inf.exit_pos[0] = float(ex); inf.exit_pos[1] = float(ey); inf.exit_pos[2] = float(ez);
+    inf.exit_pos[0] = float(R.rx); inf.exit_pos[1] = float(R.ry); inf.exit_pos[2] = float(R.rz);
     inf.tau = float(R.tau);
     inf.ln_s_end = float(R.lns);
-    const float re = float(sqrt(ex * ex + ey * ey + ez * ez));
-    inf.r_min = fminf(R.rmin, re);
+    inf.r_min = fminf(R.rmin, float(sqrt(R.rx * R.rx + R.ry * R.ry + R.rz * R.rz)));
     a.info[R.id] = inf;
   }
   if (R.path_slot >= 0) a.path_len[R.path_slot] = R.path_len;
 }
 
+// Segment factor of the exact transfer update over one segment, in FP32:
+// phi = (1 - e^{-x}) / x (series below |x| = 1/16).
+__device__ __forceinline__ float segment_phi(float x) {
+  if (fabsf(x) <= 0.0625f) {
+    float s = 1.0f / 720.0f;
+    s = fmaf(s, -x, 1.0f / 120.0f);
+    s = fmaf(s, -x, 1.0f / 24.0f);
+    s = fmaf(s, -x, 1.0f / 6.0f);
+    s = fmaf(s, -x, 0.5f);
+    return fmaf(s, -x, 1.0f);
+  }
+  return (1.0f - __builtin_amdgcn_exp2f(-1.44269504089f * x)) / x;
+}
+
 // One central RK4 step with its two perturbed retraces, termination test and
-// transfer segment.  Returns the termination code (kRunning to continue).
+// transfer segment.  Returns the termination code (kRunning to continue); on
+// termination R holds the end point, the code and the last-step fraction.
 template <bool MIXED, int KIND>
 __device__ int ray_step(const TraceArgs& a, RayState& R, CellCache& C) {
   using Real = typename RealOf<MIXED>::T;
-  const DevModelPtrs& M = a.models[R.model];
   const bool refr = (a.flags & RT_USE_REFRACTION) != 0;
   const bool mag = refr && (a.flags & RT_USE_MAGNIFICATION) != 0;
 
-  // All evaluation points of this step are r_i + (FP32 offset); forces and stage
-  // offsets are FP32, the state r_i, p_i accumulates in FP64.
+  // All evaluation points of this step are r_i + (FP32 offset).
   StepOrigin O;
-  make_origin<KIND>(a.g, R.rx, R.ry, R.rz, O);
+  make_origin<KIND>(R, O);
   const float pxf = float(R.px), pyf = float(R.py), pzf = float(R.pz);
   float h;
   double hd;
@@ -387,105 +581,107 @@ __device__ int ray_step(const TraceArgs& a, RayState& R, CellCache& C) {
   float F1x = 0.f, F1y = 0.f, F1z = 0.f, F2x = 0.f, F2y = 0.f, F2z = 0.f, F3x = 0.f, F3y = 0.f, F3z = 0.f;
   if (refr) {
     // Stage 1 at r_i also sets the step: dt = ds_max / max(n(r_i), n_floor).
-    float ne, g1x, g1y, g1z, gx, gy, gz;
-    eval_grad<KIND>(a.g, M, C, O, 0.f, 0.f, 0.f, ne, g1x, g1y, g1z);
-    F1x = R.cf * g1x; F1y = R.cf * g1y; F1z = R.cf * g1z;
+    float ne, gx, gy, gz;
+    eval_grad<KIND>(a.g, R.nfg, R.te, C, O, 0.f, 0.f, 0.f, ne, gx, gy, gz);
+    F1x = R.cf * gx; F1y = R.cf * gy; F1z = R.cf * gz;
+    float sx = gx, sy = gy, sz = gz;                  // g1 + g2 + g3
+    float tx = gx, ty = gy, tz = gz;                  // g1 + 2 g2 + 2 g3 + g4
     const float n2 = 1.0f - R.xff * ne;
     const float ni = n2 > 0.f ? sqrtf(n2) : 0.f;
-    // the FP64 step enters the state update; its FP32 rounding drives the stages
-    hd = (ni > a.n_floor) ? a.ds_max_d / double(ni) : a.ds_max_d / a.n_floor_d;
+    hd = (ni > a.n_floor) ? a.ds_max_d * rcp64(double(ni)) : a.ds_max_d / a.n_floor_d;
     h = float(hd);
     const float hh = 0.5f * h;
     d2x = hh * pxf; d2y = hh * pyf; d2z = hh * pzf;
-    float g2x, g2y, g2z;
-    eval_grad<KIND>(a.g, M, C, O, d2x, d2y, d2z, ne, g2x, g2y, g2z);
-    F2x = R.cf * g2x; F2y = R.cf * g2y; F2z = R.cf * g2z;
+    eval_grad<KIND>(a.g, R.nfg, R.te, C, O, d2x, d2y, d2z, ne, gx, gy, gz);
+    F2x = R.cf * gx; F2y = R.cf * gy; F2z = R.cf * gz;
+    sx += gx; sy += gy; sz += gz;
+    tx = fmaf(2.f, gx, tx); ty = fmaf(2.f, gy, ty); tz = fmaf(2.f, gz, tz);
     d3x = hh * (pxf + hh * F1x); d3y = hh * (pyf + hh * F1y); d3z = hh * (pzf + hh * F1z);
-    float g3x, g3y, g3z;
-    eval_grad<KIND>(a.g, M, C, O, d3x, d3y, d3z, ne, g3x, g3y, g3z);
-    F3x = R.cf * g3x; F3y = R.cf * g3y; F3z = R.cf * g3z;
-    const float d4x = h * (pxf + hh * F2x), d4y = h * (pyf + hh * F2y), d4z = h * (pzf + hh * F2z);
-    eval_grad<KIND>(a.g, M, C, O, d4x, d4y, d4z, ne, gx, gy, gz);
+    eval_grad<KIND>(a.g, R.nfg, R.te, C, O, d3x, d3y, d3z, ne, gx, gy, gz);
+    F3x = R.cf * gx; F3y = R.cf * gy; F3z = R.cf * gz;
+    sx += gx; sy += gy; sz += gz;
+    tx = fmaf(2.f, gx, tx); ty = fmaf(2.f, gy, ty); tz = fmaf(2.f, gz, tz);
+    eval_grad<KIND>(a.g, R.nfg, R.te, C, O, h * (pxf + hh * F2x), h * (pyf + hh * F2y), h * (pzf + hh * F2z), ne, gx,
+                    gy, gz);
+    tx += gx; ty += gy; tz += gz;
     // RK4: dr = h p + h^2/6 (F1 + F2 + F3), dp = h/6 (F1 + 2 F2 + 2 F3 + F4),
-    // F = -1/2 Xf grad n_e with the coefficient applied in FP64.
+    // F = -1/2 Xf grad n_e, the coefficient applied in FP64.
     const double c6 = R.cfd * hd * (1.0 / 6.0);
-    drx = hd * R.px + hd * c6 * double(g1x + g2x + g3x);
-    dry = hd * R.py + hd * c6 * double(g1y + g2y + g3y);
-    drz = hd * R.pz + hd * c6 * double(g1z + g2z + g3z);
-    dpx = c6 * double(g1x + 2.f * g2x + 2.f * g3x + gx);
-    dpy = c6 * double(g1y + 2.f * g2y + 2.f * g3y + gy);
-    dpz = c6 * double(g1z + 2.f * g2z + 2.f * g3z + gz);
+    drx = hd * R.px + hd * c6 * double(sx);
+    dry = hd * R.py + hd * c6 * double(sy);
+    drz = hd * R.pz + hd * c6 * double(sz);
+    dpx = c6 * double(tx);
+    dpy = c6 * double(ty);
+    dpz = c6 * double(tz);
   } else {
     // Straight line of sight: no force, |p| = 1, dt = ds_max.
     h = a.ds_max;
     hd = a.ds_max_d;
-    drx = a.ds_max_d * R.px; dry = a.ds_max_d * R.py; drz = a.ds_max_d * R.pz;
+    drx = hd * R.px; dry = hd * R.py; drz = hd * R.pz;
   }
+  R.n += 1;
   if (!(isfinite(drx) && isfinite(dry) && isfinite(drz) && isfinite(dpx) && isfinite(dpy) && isfinite(dpz))) {
-    R.n += 1;
-    finish_ray<Real>(a, R, kNonfinite, Real(R.rx), Real(R.ry), Real(R.rz), Real(1));
+    R.code = kNonfinite;
+    R.lam_end = 1.0f;
     return kNonfinite;
   }
+  R.px += dpx; R.py += dpy; R.pz += dpz;  // p is not used again in this step
 
   // Eq. 5: chord direction (the chord is exactly the increment dr).
   const Real dx = Real(drx), dy = Real(dry), dz = Real(drz);
   const Real ds = sqrt(dx * dx + dy * dy + dz * dz);
-  Real lnM = Real(0);
+  float lnM = 0.0f;
   if (mag) {
-    const Real tx = dx / ds, ty = dy / ds, tz = dz / ds;
+    const Real inv_ds = Real(1) / ds;
+    const Real tx = dx * inv_ds, ty = dy * inv_ds, tz = dz * inv_ds;
     // Eq. 6: a = z unless |t_z| is near 1, then y; e1 = a x t / |a x t|, e2 = t x e1.
     Real c1x, c1y, c1z;
     if (fabs(tz) > Real(0.9)) { c1x = tz; c1y = Real(0); c1z = -tx; }
     else { c1x = -ty; c1y = tx; c1z = Real(0); }
     const Real ci = Real(1) / sqrt(c1x * c1x + c1y * c1y + c1z * c1z);
     const Real e1x = c1x * ci, e1y = c1y * ci, e1z = c1z * ci;
-    const Real e2x = ty * e1z - tz * e1y, e2y = tz * e1x - tx * e1z, e2z = tx * e1y - ty * e1x;
     const Real eps = Real(a.eta) * ds;  // Eq. 8
     // Eqs. 7 and 9 in difference form: the perturbed ray starts at r_i + eps e_j with
     // the central wavevector; its RK4 end point minus the central one is
     // eps e_j + h^2/6 (dF1 + dF2 + dF3), dF_k the force differences at the first
     // three stages (the fourth stage only moves p, which is discarded).
-    Real sep[2][3];
-#pragma unroll
+    const float hh = 0.5f * h, hq = hh * hh, hh6 = h * h * (1.0f / 6.0f);
+    Real s1x = 0, s1y = 0, s1z = 0, det = 0;
+#pragma unroll 1
     for (int jj = 0; jj < 2; ++jj) {
-      const Real ex = jj == 0 ? e1x : e2x, ey = jj == 0 ? e1y : e2y, ez = jj == 0 ? e1z : e2z;
+      Real ex = e1x, ey = e1y, ez = e1z;
+      if (jj == 1) { ex = ty * e1z - tz * e1y; ey = tz * e1x - tx * e1z; ez = tx * e1y - ty * e1x; }
       const Real d0x = eps * ex, d0y = eps * ey, d0z = eps * ez;
       const float fx = float(d0x), fy = float(d0y), fz = float(d0z);
-      const float hh = 0.5f * h;
       float ne, gx, gy, gz;
-      eval_grad<KIND>(a.g, M, C, O, fx, fy, fz, ne, gx, gy, gz);
+      eval_grad<KIND>(a.g, R.nfg, R.te, C, O, fx, fy, fz, ne, gx, gy, gz);
       const float q1x = R.cf * gx - F1x, q1y = R.cf * gy - F1y, q1z = R.cf * gz - F1z;
-      eval_grad<KIND>(a.g, M, C, O, d2x + fx, d2y + fy, d2z + fz, ne, gx, gy, gz);
-      const float q2x = R.cf * gx - F2x, q2y = R.cf * gy - F2y, q2z = R.cf * gz - F2z;
-      const float hq = hh * hh;
-      eval_grad<KIND>(a.g, M, C, O, d3x + fx + hq * q1x, d3y + fy + hq * q1y, d3z + fz + hq * q1z, ne, gx, gy, gz);
-      const float q3x = R.cf * gx - F3x, q3y = R.cf * gy - F3y, q3z = R.cf * gz - F3z;
-      const float hh6 = h * h * (1.0f / 6.0f);
-      sep[jj][0] = d0x + Real(hh6 * (q1x + q2x + q3x));
-      sep[jj][1] = d0y + Real(hh6 * (q1y + q2y + q3y));
-      sep[jj][2] = d0z + Real(hh6 * (q1z + q2z + q3z));
+      eval_grad<KIND>(a.g, R.nfg, R.te, C, O, d2x + fx, d2y + fy, d2z + fz, ne, gx, gy, gz);
+      float ax = q1x + (R.cf * gx - F2x), ay = q1y + (R.cf * gy - F2y), az = q1z + (R.cf * gz - F2z);
+      eval_grad<KIND>(a.g, R.nfg, R.te, C, O, d3x + fx + hq * q1x, d3y + fy + hq * q1y, d3z + fz + hq * q1z, ne, gx,
+                      gy, gz);
+      ax += R.cf * gx - F3x; ay += R.cf * gy - F3y; az += R.cf * gz - F3z;
+      const Real sx = d0x + Real(hh6 * ax), sy = d0y + Real(hh6 * ay), sz = d0z + Real(hh6 * az);
+      if (jj == 0) { s1x = sx; s1y = sy; s1z = sz; }
+      else det = (s1y * sz - s1z * sy) * tx + (s1z * sx - s1x * sz) * ty + (s1x * sy - s1y * sx) * tz;
     }
-    // Eqs. 10-11: M = |(dr1 x dr2) . t| / eps^2.
-    const Real cx = sep[0][1] * sep[1][2] - sep[0][2] * sep[1][1];
-    const Real cy = sep[0][2] * sep[1][0] - sep[0][0] * sep[1][2];
-    const Real cz = sep[0][0] * sep[1][1] - sep[0][1] * sep[1][0];
-    const Real area = fabs(cx * tx + cy * ty + cz * tz);
-    lnM = log(area / (eps * eps));
+    // Eqs. 10-11: M = |(dr1 x dr2) . t| / eps^2; ln M from the accurately formed M - 1.
+    const Real mm1 = fabs(det) / (eps * eps) - Real(1);
+    lnM = fast_log1pf(float(mm1));
   }
 
   // Termination on the two spheres, last chord truncated at the crossing.
-  const Real ox = Real(R.rx), oy = Real(R.ry), oz = Real(R.rz);
-  const Real nx = ox + dx, ny = oy + dy, nz = oz + dz;
-  const Real r1sq = nx * nx + ny * ny + nz * nz;
+  const double nx = R.rx + drx, ny = R.ry + dry, nz = R.rz + drz;
+  const double r1sq = nx * nx + ny * ny + nz * nz;
   int code = kRunning;
-  Real lam = Real(1);
-  if (a.g.has_inner && r1sq <= Real(a.g.r_in * a.g.r_in)) {
+  double lam = 1.0;
+  if (a.g.has_inner && r1sq <= a.g.r_in * a.g.r_in) {
     code = kHit;
-    lam = crossing<Real>(ox, oy, oz, dx, dy, dz, a.g.r_in, false);
-  } else if (r1sq >= Real(a.g.r_max * a.g.r_max) && R.n >= 1) {
+    lam = crossing<double>(R.rx, R.ry, R.rz, drx, dry, drz, a.g.r_in, false);
+  } else if (r1sq >= a.g.r_max * a.g.r_max && R.n >= 2) {
     code = kExit;
-    lam = crossing<Real>(ox, oy, oz, dx, dy, dz, a.g.r_max, true);
-  } else if (R.n + 1 == a.max_steps) {
+    lam = crossing<double>(R.rx, R.ry, R.rz, drx, dry, drz, a.g.r_max, true);
+  } else if (R.n == a.max_steps) {
     code = kMaxSteps;
   }
 
@@ -493,41 +689,44 @@ __device__ int ray_step(const TraceArgs& a, RayState& R, CellCache& C) {
   // gamma = -lam ln M (the d ln S/ds term over the segment, in the transfer direction).
   const float hl = 0.5f * float(lam);
   float ne_m, te_m;
-  eval_value<KIND>(a.g, M, C, O, hl * float(drx), hl * float(dry), hl * float(drz), ne_m, te_m);
+  eval_value<KIND>(a.g, R.nfg, R.te, C, O, hl * float(drx), hl * float(dry), hl * float(drz), ne_m, te_m);
   Real dtau = Real(0);
   if (!(a.flags & RT_TEST_NO_ABSORPTION)) {
-    const float lt = logf(te_m);
+    const float lt = __builtin_amdgcn_logf(te_m) * 0.69314718056f;
     const float lnl = (te_m >= 2.0e5f) ? 24.5f + lt - R.lnf : 18.2f + 1.5f * lt - R.lnf;
-    const float kn = kFFCoefF * ne_m * ne_m * lnl / (R.f2 * te_m * sqrtf(te_m));
-    dtau = Real(kn) * Real(kRsunCm) * lam * Real(hd);
+    const float kn = kFFCoefF * ne_m * ne_m * lnl * rcpf(R.f2 * te_m * sqrtf(te_m));
+    dtau = Real(kn) * Real(kRsunCm * lam * hd);
   }
-  const Real gamma = -(lam * lnM);
+  const Real gamma = -Real(lam) * Real(lnM);
   const Real xs = dtau + gamma;
-  const Real em = expm1(-xs);
-  const Real phi = (xs == Real(0)) ? Real(1) : -em / xs;
-  R.A += R.P * double(Real(te_m) * dtau * phi);
-  R.P *= double(Real(1) + em);
-  R.tau += double(dtau);
-  R.lns += double(lam * lnM);
-  R.s_arc += double(lam * ds);
-  R.n += 1;
+  // front to back: A += e^{-Lambda} T dtau phi(x), Lambda += x; the transmittance
+  // is formed from the accumulated Lambda each step, so its error does not compound
+  const float trans = __builtin_amdgcn_exp2f(-1.44269504089f * float(R.lam_tot));
+  R.A = double(Real(R.A) + Real(trans) * (Real(te_m) * dtau * Real(segment_phi(float(xs)))));
+  R.lam_tot = double(Real(R.lam_tot) + xs);
+  R.tau = double(Real(R.tau) + dtau);
+  R.lns = double(Real(R.lns) + Real(lam) * Real(lnM));
 
-  if (R.path_slot >= 0 && R.path_len < a.path_cap) {
-    float* rec = a.path_out + (size_t(R.path_slot) * a.path_cap + R.path_len) * kPathStride;
-    rec[0] = float(ox + lam * dx); rec[1] = float(oy + lam * dy); rec[2] = float(oz + lam * dz);
-    rec[3] = float(R.s_arc); rec[4] = float(lnM); rec[5] = float(lnM / ds);
-    rec[6] = float(R.tau); rec[7] = ne_m; rec[8] = te_m;
-    R.path_len += 1;
+  if (R.path_slot >= 0) {
+    R.s_arc += lam * double(ds);
+    if (R.path_len < a.path_cap) {
+      float* rec = a.path_out + (size_t(R.path_slot) * a.path_cap + R.path_len) * kPathStride;
+      rec[0] = float(R.rx + lam * drx); rec[1] = float(R.ry + lam * dry); rec[2] = float(R.rz + lam * drz);
+      rec[3] = float(R.s_arc); rec[4] = lnM; rec[5] = lnM / float(ds);
+      rec[6] = float(R.tau); rec[7] = ne_m; rec[8] = te_m;
+      R.path_len += 1;
+    }
   }
 
   if (code != kRunning) {
-    finish_ray<Real>(a, R, code, ox + lam * dx, oy + lam * dy, oz + lam * dz, lam);
+    R.rx += lam * drx; R.ry += lam * dry; R.rz += lam * drz;
+    R.code = code;
+    R.lam_end = float(lam);
     return code;
   }
-  R.rx += drx; R.ry += dry; R.rz += drz;
-  R.px += dpx; R.py += dpy; R.pz += dpz;
-  const float rr = float(sqrt(R.rx * R.rx + R.ry * R.ry + R.rz * R.rz));
-  R.rmin = fminf(R.rmin, rr);
+  index_advance<KIND>(a.g, R, drx, dry, drz);
+  R.rx = nx; R.ry = ny; R.rz = nz;
+  R.rmin = fminf(R.rmin, float(sqrt(r1sq)));
   return kRunning;
 }
 
