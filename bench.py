@@ -28,11 +28,12 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 # Algorithmic FP32/FP64 operations per ray-step of the method (counted on the
-# method's arithmetic, not on compiled code; derivation in the design notes):
-#   10 force evaluations x 137 + 1 value evaluation x 76 + RK4 combinations 66 +
-#   step rule 4 + basis 35 + perturbed offsets/differences 2 x 41 + area 18 +
-#   termination 6 + midpoint offset 6 + free-free 10 + transfer 18  = 1,691.
-FLOPS_PER_RAY_STEP = 1691
+# method's arithmetic, not on compiled code; FMA = 2, each transcendental = 1):
+#   4 central force evaluations x 128 + RK4 offsets/step rule/increments 74 +
+#   2 perturbed retracings x 417 (3 force evaluations each with offsets and
+#   differences) + basis 30 + area and ln M 18 + termination 7 + midpoint value
+#   evaluation 72 + free-free 14 + transfer 15 = 1,576.
+FLOPS_PER_RAY_STEP = 1576
 # MI355X vector peak without packed FP32 (the build compiles it out):
 # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz = 78.6 TFLOP/s (FP32 and FP64 alike).
 VALU_PEAK_TFLOPS = 78.6
