@@ -37,6 +37,22 @@ FLOPS_PER_RAY_STEP = 1576
 # MI355X vector peak without packed FP32 (the build compiles it out):
 # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz = 78.6 TFLOP/s (FP32 and FP64 alike).
 VALU_PEAK_TFLOPS = 78.6
+# HBM bytes per launch of the persistent tracer on this workload, from rocprofv3
+# FETCH_SIZE / WRITE_SIZE passes scaled by a 1 GiB copy (read x2.000, write x1.000),
+# valid only for the kernel sources they were taken on (hash below); reported as
+# null as soon as those sources change.
+KERNEL_SOURCES = ("rt_trace.hpp", "rt_kernels.hip", "rt_internal.hpp")
+TRAFFIC = {"sources_sha256_16": "352d79bc859cc874", "read_bytes": 2667213 * 1024 * 2.0,
+           "write_bytes": 15429 * 1024 * 1.0}
+
+
+def kernel_sources_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2606_02413_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def parse():
@@ -151,8 +167,13 @@ def main():
                  "bitwise_equal_to_batched": same}
 
     achieved_tflops = FLOPS_PER_RAY_STEP * rate / 1e12
+    traffic = None
+    if kernel_sources_hash() == TRAFFIC["sources_sha256_16"]:
+        traffic = {"read_bytes": TRAFFIC["read_bytes"], "write_bytes": TRAFFIC["write_bytes"],
+                   "bytes": TRAFFIC["read_bytes"] + TRAFFIC["write_bytes"],
+                   "GB/s": round((TRAFFIC["read_bytes"] + TRAFFIC["write_bytes"]) / (ms_per_step * 1e-3) / 1e9, 2)}
     roofline = {"bound": "alu", "achieved": round(achieved_tflops, 3), "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved_tflops / VALU_PEAK_TFLOPS, 4), "traffic": None,
+                "frac": round(achieved_tflops / VALU_PEAK_TFLOPS, 4), "traffic": traffic,
                 "kernel": "k_trace_persistent<mixed, spherical>", "flops_per_ray_step": FLOPS_PER_RAY_STEP,
                 "kernel_ms": round(ms_per_step, 3)}
     cpu = None if args.no_cpu else cpu_baseline(cor, wl, args.cpu_seconds)
