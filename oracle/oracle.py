@@ -91,6 +91,8 @@ def lib():
         L.orc_kappa_n.argtypes = [C.c_int, dp, dp, C.c_double, dp]
         L.orc_dual_loss.argtypes = [C.POINTER(Medium), C.POINTER(Params), C.POINTER(Image), C.c_int, dp,
                                     C.POINTER(C.c_float), dp, dp, dp, dp, C.c_int]
+        L.orc_grad_loss.argtypes = [C.POINTER(Medium), C.POINTER(Params), C.POINTER(Image), C.c_int, dp,
+                                    C.POINTER(C.c_float), dp, dp, dp, C.c_int]
         _lib = L
     return _lib
 
@@ -231,3 +233,20 @@ def dual_loss(med, params, image, freqs, weights, vn=None, vt=None, n_threads=No
                              C.byref(loss), C.byref(dl), n_threads or default_threads())
     assert rc == 0
     return loss.value, dl.value
+
+
+def grad_loss(med, params, image, freqs, weights, n_threads=None):
+    """(loss, d loss / d ln n_e, d loss / d ln T) of loss = sum w*T_b by reverse-mode
+    sweeps of per-ray tapes; weights are [n_freq][nv][nu] (zero weights skip the ray)
+    and the gradients have the grid's shape."""
+    freqs = np.ascontiguousarray(freqs, dtype=np.float64)
+    w = np.ascontiguousarray(weights, dtype=np.float32)
+    shape = (med.struct.n0, med.struct.n1, med.struct.n2)
+    gne = np.zeros(shape, dtype=np.float64)
+    gte = np.zeros(shape, dtype=np.float64)
+    loss = C.c_double(0)
+    rc = lib().orc_grad_loss(C.byref(med.struct), C.byref(params), C.byref(image), freqs.shape[0], _dptr(freqs),
+                             w.ctypes.data_as(C.POINTER(C.c_float)), C.byref(loss), _dptr(gne), _dptr(gte),
+                             n_threads or default_threads())
+    assert rc == 0
+    return loss.value, gne, gte

@@ -35,6 +35,7 @@
 #include <cstring>
 #include <limits>
 #include <thread>
+#include <type_traits>
 #include <vector>
 
 namespace orc {
@@ -80,6 +81,83 @@ inline double val(double x) { return x; }
 inline double val(const Dual& x) { return x.v; }
 inline bool finite_s(double x) { return std::isfinite(x); }
 inline bool finite_s(const Dual& x) { return std::isfinite(x.v); }
+
+// ---------------------------------------------------------------------------
+// Reverse-mode scalar on a per-thread tape.  Every operation whose operands are
+// not all constants appends one node (up to two parents and the local partial
+// derivatives); a model value read from the grid appends a leaf node that names
+// its vertex and whether it is n_e or T, with the partial d value / d ln value.
+// One ray is recorded, swept backward from its output, then the tape is reset.
+// ---------------------------------------------------------------------------
+constexpr int32_t kNoParent = -1, kLeafNe = -2, kLeafTe = -3;
+struct TapeNode {
+  int32_t a, b;      // parents (node indices), or kNoParent; a leaf has a = kLeafNe / kLeafTe, b = vertex
+  double da, db;     // partial derivatives w.r.t. a and b
+};
+struct Tape {
+  std::vector<TapeNode> nodes;
+};
+inline Tape*& tape_ref() {
+  static thread_local Tape* t = nullptr;
+  return t;
+}
+struct Rev {
+  double v = 0;
+  int32_t i = kNoParent;  // node index; kNoParent for a constant
+  Rev() = default;
+  Rev(double x) : v(x), i(kNoParent) {}
+};
+inline Rev rev_node(double v, int32_t a, double da, int32_t b, double db) {
+  if (a == kNoParent && b == kNoParent) return Rev(v);
+  Tape* t = tape_ref();
+  if (a == kNoParent) { a = b; da = db; b = kNoParent; db = 0.0; }
+  t->nodes.push_back({a, b, da, db});
+  Rev r(v);
+  r.i = int32_t(t->nodes.size() - 1);
+  return r;
+}
+inline Rev rev_leaf(double v, int32_t kind, size_t vertex) {
+  Tape* t = tape_ref();
+  t->nodes.push_back({kind, int32_t(vertex), v, 0.0});
+  Rev r(v);
+  r.i = int32_t(t->nodes.size() - 1);
+  return r;
+}
+inline Rev operator+(Rev a, Rev b) { return rev_node(a.v + b.v, a.i, 1.0, b.i, 1.0); }
+inline Rev operator-(Rev a, Rev b) { return rev_node(a.v - b.v, a.i, 1.0, b.i, -1.0); }
+inline Rev operator-(Rev a) { return rev_node(-a.v, a.i, -1.0, kNoParent, 0.0); }
+inline Rev operator*(Rev a, Rev b) { return rev_node(a.v * b.v, a.i, b.v, b.i, a.v); }
+inline Rev operator/(Rev a, Rev b) { return rev_node(a.v / b.v, a.i, 1.0 / b.v, b.i, -a.v / (b.v * b.v)); }
+inline Rev sqrt(Rev a) { double s = std::sqrt(a.v); return rev_node(s, a.i, 0.5 / s, kNoParent, 0.0); }
+inline Rev exp(Rev a) { double e = std::exp(a.v); return rev_node(e, a.i, e, kNoParent, 0.0); }
+inline Rev expm1(Rev a) { return rev_node(std::expm1(a.v), a.i, std::exp(a.v), kNoParent, 0.0); }
+inline Rev log(Rev a) { return rev_node(std::log(a.v), a.i, 1.0 / a.v, kNoParent, 0.0); }
+inline Rev pow(Rev a, double k) { return rev_node(std::pow(a.v, k), a.i, k * std::pow(a.v, k - 1.0), kNoParent, 0.0); }
+inline Rev atan2(Rev y, Rev x) {
+  double r2 = x.v * x.v + y.v * y.v;
+  return rev_node(std::atan2(y.v, x.v), y.i, x.v / r2, x.i, -y.v / r2);
+}
+inline Rev fabs(Rev a) { return a.v < 0 ? -a : a; }
+inline double val(const Rev& x) { return x.v; }
+inline bool finite_s(const Rev& x) { return std::isfinite(x.v); }
+
+// Backward sweep of the current tape from node `out` with seed `w`; leaf
+// adjoints (already d/d ln) are added to gne / gte.
+inline void rev_sweep(const Rev& out, double w, double* gne, double* gte, std::vector<double>& adj) {
+  Tape* t = tape_ref();
+  if (out.i == kNoParent) return;
+  adj.assign(size_t(out.i) + 1, 0.0);
+  adj[size_t(out.i)] = w;
+  for (int64_t k = out.i; k >= 0; --k) {
+    const double g = adj[size_t(k)];
+    if (g == 0.0) continue;
+    const TapeNode& nd = t->nodes[size_t(k)];
+    if (nd.a == kLeafNe) { gne[nd.b] += g * nd.da; continue; }
+    if (nd.a == kLeafTe) { gte[nd.b] += g * nd.da; continue; }
+    if (nd.a >= 0) adj[size_t(nd.a)] += g * nd.da;
+    if (nd.b >= 0) adj[size_t(nd.b)] += g * nd.db;
+  }
+}
 
 // ---------------------------------------------------------------------------
 // Small vector helpers.
@@ -161,6 +239,13 @@ struct DualSource {
     double x = m->te[i];
     return S(x, vt ? x * vt[i] : 0.0);
   }
+};
+
+// Model values as tape leaves (gradient w.r.t. ln n_e and ln T per vertex).
+struct RevSource {
+  const Medium* m;
+  template <class S> S ne(size_t i) const { return rev_leaf(double(m->ne[i]), kLeafNe, i); }
+  template <class S> S te(size_t i) const { return rev_leaf(double(m->te[i]), kLeafTe, i); }
 };
 
 template <class S> struct Sample {
@@ -534,7 +619,7 @@ RayOut<S> trace_rk4(const Medium& m, const Src& src, const Params& P, double f,
     rmin = std::min(rmin, vnorm(r));
     min_axis = std::min(min_axis, axis_angle(r));
     if (L0 > 0.0) bdrift = std::max(bdrift, std::fabs(vnorm(cross(r, p)) - L0) / L0);
-    if (refr) {
+    if (refr && std::is_same<S, double>::value) {  // diagnostic only: kept off the AD tapes
       Sample<S> sh = eval_medium(m, src, r, false);
       hdrift = std::max(hdrift, std::fabs(val(dot(p, p)) + xf * val(sh.ne) - 1.0));
     }
@@ -896,6 +981,7 @@ int orc_dual_loss(const Medium* m, const Params* P, const Image* im, int n_freq,
   parallel_for(n, n_threads, [&](int k) {
     int fi = k / npx, px = k % npx;
     int ju = px % im->nu, iv = px / im->nu;
+    if (w[k] == 0.0f) return;  // contributes nothing
     Launch L = pixel_launch(*im, m->r_max, ju, iv, 0.0);
     if (L.b >= m->r_max) { lv[size_t(k)] = w[k] * P->tb_sky; return; }
     RayOut<Dual> ro = trace_rk4<Dual>(*m, src, *P, freqs[fi], L.r0, L.dir, nullptr, 0, nullptr);
@@ -906,6 +992,59 @@ int orc_dual_loss(const Medium* m, const Params* P, const Image* im, int n_freq,
   for (int k = 0; k < n; ++k) { s += lv[size_t(k)]; sd += ld[size_t(k)]; }
   *loss = s;
   *dloss = sd;
+  return 0;
+}
+
+// Gradient of sum_k w_k T_b,k over the rays of an image stack (k = freq * npx +
+// pixel; rays with w_k = 0 are skipped) w.r.t. ln n_e and ln T at every vertex,
+// by reverse-mode sweeps of per-ray tapes.  gne / gte [n0 n1 n2] are overwritten.
+int orc_grad_loss(const Medium* m, const Params* P, const Image* im, int n_freq, const double* freqs,
+                  const float* w, double* loss, double* gne, double* gte, int n_threads) {
+  if (!m || !P || !im || !freqs || !w || !loss || !gne || !gte || n_freq < 1) return 1;
+  if (m->kind != GRID_SPHERICAL_LOGR && m->kind != GRID_CARTESIAN) return 1;
+  const int npx = im->nu * im->nv;
+  const int n = npx * n_freq;
+  const size_t nv = size_t(m->n0) * m->n1 * m->n2;
+  if (n_threads < 1) n_threads = 1;
+  const size_t nth = size_t(n_threads);
+  std::vector<std::vector<double>> part_ne(nth), part_te(nth);
+  std::vector<double> part_loss(size_t(n_threads), 0.0);
+  std::atomic<int> next(0);
+  RevSource src{m};
+  auto worker = [&](int tid) {
+    Tape tape;
+    tape_ref() = &tape;
+    std::vector<double> adj;
+    std::vector<double>& g1 = part_ne[size_t(tid)];
+    std::vector<double>& g2 = part_te[size_t(tid)];
+    g1.assign(nv, 0.0);
+    g2.assign(nv, 0.0);
+    for (;;) {
+      const int k = next.fetch_add(1);
+      if (k >= n) break;
+      if (w[k] == 0.0f) continue;
+      const int fi = k / npx, px = k % npx;
+      Launch L = pixel_launch(*im, m->r_max, px % im->nu, px / im->nu, 0.0);
+      if (L.b >= m->r_max) { part_loss[size_t(tid)] += double(w[k]) * P->tb_sky; continue; }
+      tape.nodes.clear();
+      RayOut<Rev> ro = trace_rk4<Rev>(*m, src, *P, freqs[fi], L.r0, L.dir, nullptr, 0, nullptr);
+      part_loss[size_t(tid)] += double(w[k]) * ro.tb.v;
+      if (ro.code != NONFINITE) rev_sweep(ro.tb, double(w[k]), g1.data(), g2.data(), adj);
+    }
+    tape_ref() = nullptr;
+  };
+  std::vector<std::thread> pool;
+  for (int t = 0; t < n_threads; ++t) pool.emplace_back(worker, t);
+  for (auto& th : pool) th.join();
+  double s = 0.0;
+  for (int t = 0; t < n_threads; ++t) s += part_loss[size_t(t)];
+  *loss = s;
+  for (size_t v = 0; v < nv; ++v) {
+    double a = 0.0, b = 0.0;
+    for (int t = 0; t < n_threads; ++t) { a += part_ne[size_t(t)][v]; b += part_te[size_t(t)][v]; }
+    gne[v] = a;
+    gte[v] = b;
+  }
   return 0;
 }
 
