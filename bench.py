@@ -62,6 +62,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-plain", action="store_true", help="skip the plain per-frequency timing")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint / forward timing")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (reference for HBM byte counters)")
@@ -104,6 +105,40 @@ def cpu_baseline(cor, wl, seconds):
     return {"value": steps / dt, "unit": "ray-steps/s", "cores": threads, "kind": "oracle",
             "sample": f"{rays} rays ({rays // len(wl.freqs)} seeded pixels x {len(wl.freqs)} freq) of the "
                       f"structured workload, {steps} ray-steps in {dt:.1f} s"}
+
+
+def adjoint_ratio(R, torch, model, stream, reps=2):
+    """Adjoint workload: the same model, 256^2 image over +/-3 R_sun, the 8
+    frequencies, K = 64, loss weights w ~ U[0, 1) (seed 1000).  Forward = the
+    persistent rt_trace_maps launch on that image; adjoint = rt_trace_adjoint
+    (forward with checkpoints + reverse sweep + gradient gather)."""
+    from paper_2606_02413_amd import corona
+    wl = corona.workload("adjoint")
+    im = R.image_desc(wl.n_pix, wl.half_width)
+    prm = R.params(ds_max=wl.ds_max, n_floor=wl.n_floor, max_steps=wl.max_steps, checkpoint_every=64)
+    w = torch.from_numpy(corona.seeded_weights((len(wl.freqs), wl.n_pix, wl.n_pix), 1000)).cuda()
+    fwd = R.trace_maps([model], wl.freqs, im, prm, info=False, stats=True)
+    adj = R.trace_adjoint(model, wl.freqs, im, prm, w)
+    torch.cuda.synchronize()
+
+    def timed(fn):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    f_ms = timed(lambda: R.trace_maps([model], wl.freqs, im, prm, info=False, stats=True, out=fwd))
+    a_ms = timed(lambda: R.trace_adjoint(model, wl.freqs, im, prm, w, out=adj))
+    steps = int(R.decode_stats(fwd["stats"])["ray_steps"])
+    diff = float(((adj["tb"].double() - fwd["tb"][0].double()).abs() / fwd["tb"][0].double().abs().clamp(min=1.0)).max())
+    return {"workload": f"adjoint: {wl.n_pix}^2 image x {len(wl.freqs)} freq, same model, K = 64, w ~ U[0,1)",
+            "forward_ms": f_ms, "adjoint_ms": a_ms, "ratio": a_ms / f_ms, "ray_steps": steps,
+            "adjoint_ray_steps_per_s": steps / (a_ms * 1e-3), "maps_max_rel_diff": diff,
+            "loss": float(adj["loss"].cpu()[0])}
 
 
 def main():
@@ -166,6 +201,8 @@ def main():
         plain = {"ms_per_step": pms, "ray_steps_per_s": steps_per_pass / (pms * 1e-3),
                  "bitwise_equal_to_batched": same}
 
+    adjoint = None if args.no_adjoint else adjoint_ratio(R, torch, model, stream)
+
     achieved_tflops = FLOPS_PER_RAY_STEP * rate / 1e12
     traffic = None
     if kernel_sources_hash() == TRAFFIC["sources_sha256_16"]:
@@ -198,7 +235,8 @@ def main():
         "batched": {"ms_per_step": ms_per_step, "ray_steps_per_s": rate},
         "plain": plain,
         "batched_over_plain": (plain["ms_per_step"] / ms_per_step) if plain else None,
-        "adjoint_fwd_ratio": None,
+        "adjoint_fwd_ratio": adjoint["ratio"] if adjoint else None,
+        "adjoint": adjoint,
         "wall_s": wall,
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -121,7 +121,7 @@ enum {
   RT_PREC_ALL_FP32 = 1u << 2,      /* area estimate and transfer in FP32 instead of FP64 */
   RT_SCHED_PLAIN = 1u << 3,        /* one launch per (model, frequency) image instead of
                                       one persistent launch over all of them */
-  RT_DETERMINISTIC_GRAD = 1u << 4, /* reserved */
+  RT_DETERMINISTIC_GRAD = 1u << 4, /* reserved (rt_trace_adjoint: RT_E_UNSUPPORTED) */
   RT_TEST_NO_ABSORPTION = 1u << 30 /* kappa = 0 (tests of I*S = const, Eq. 1) */
 };
 
@@ -131,7 +131,7 @@ typedef struct {
   double ds_max;            /* step rule dt = ds_max / max(n(r_i), n_floor) (arc length <= ds_max) */
   double n_floor;           /* in (0, 1]; 1 gives the fixed dt = ds_max of Sec. 2.1 */
   int32_t max_steps;        /* >= 1 */
-  int32_t checkpoint_every; /* adjoint: ray-state checkpoint interval K (>= 1) */
+  int32_t checkpoint_every; /* adjoint: ray-state checkpoint interval K (>= 1; 0 selects 64) */
   double perturb_ratio;     /* eta of Eq. 8, > 0 */
   double tb_inner_K;        /* boundary brightness behind a ray that reaches r_in */
   double tb_sky_K;          /* boundary brightness behind a ray that leaves (or misses) */
@@ -181,13 +181,29 @@ rt_status rt_trace_maps(const rt_model* const* models, int32_t n_models, const d
                         float* path_out, int32_t* path_len_out, void* hip_stream);
 
 /* Reverse-mode gradient of L = sum_{f,i,j} w[f][i][j] T_b[f][i][j] with
- * respect to ln n_e and ln T at every grid vertex, for one model.
- *  weights: DEVICE float32 [n_freq][nv][nu]; loss_out: DEVICE double scalar;
- *  grad_ln_ne, grad_ln_te: DEVICE float32 [n0][n1][n2], overwritten;
- *  tb_out: DEVICE float32 [n_freq][nv][nu] or NULL.
- * Ray states are checkpointed every params->checkpoint_every steps and
- * recomputed in reverse; gradients are scattered with float atomics, so
- * their summation order (and last bits) can vary between runs. */
+ * respect to ln n_e and ln T at every grid vertex, for one model: the exact
+ * derivative of the discrete forward of rt_trace_maps (Sec. 2.1 Eq. 4 ray
+ * equations, Eqs. 5-11 perturbation retracing and magnification, Eqs. 2-3 and
+ * 12 transfer with the geometric term), every discrete choice (cells, step
+ * count, termination) held fixed.
+ *  freq_hz[n_freq]: HOST array, each > 0 (n_freq <= 128).
+ *  weights: DEVICE float32 [n_freq][nv][nu] (caller-owned; rays with w = 0 are
+ *    traced forward for the loss but not swept backward).
+ *  loss_out: DEVICE double scalar, overwritten with L.
+ *  grad_ln_ne, grad_ln_te: DEVICE float32 [n0][n1][n2] (C order), overwritten.
+ *  tb_out: DEVICE float32 [n_freq][nv][nu] or NULL; the maps of rt_trace_maps
+ *    with the same params, up to rounding (the adjoint kernels are compiled
+ *    per tracing mode, so their arithmetic may be contracted differently).
+ * Each ray is traced forward with its state checkpointed every
+ * params->checkpoint_every steps (0 selects 64); a ray longer than 128
+ * checkpoints doubles its interval.  The reverse sweep recomputes each chunk of
+ * steps from its checkpoint.  Channel adjoints are accumulated per lane and cell
+ * in FP32 and added into an FP64 per-vertex accumulator with atomics, so the
+ * last bits can vary between runs.  Mixed precision only: RT_PREC_ALL_FP32,
+ * RT_DETERMINISTIC_GRAD and RT_TEST_NO_ABSORPTION return RT_E_UNSUPPORTED.  The library keeps a
+ * per-device workspace (checkpoints, step buffer, accumulator), grown on demand.
+ * Errors: RT_E_INVALID_ARG for NULL or inconsistent arguments, RT_E_CAPACITY,
+ * RT_E_OUT_OF_MEMORY, RT_E_DEVICE; nothing is written on a validation error. */
 rt_status rt_trace_adjoint(const rt_model* model, const double* freq_hz, int32_t n_freq,
                            const rt_image_desc* image, const rt_params* params, const float* weights,
                            double* loss_out, float* grad_ln_ne, float* grad_ln_te, float* tb_out,

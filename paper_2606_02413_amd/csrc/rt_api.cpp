@@ -72,8 +72,11 @@ struct DeviceScratch {
   size_t start_cap = 0;          // pixels
   float* start_ne = nullptr;     // per-(model, pixel) n_e at the start point
   size_t start_ne_cap = 0;
+  void* adj_ws = nullptr;        // adjoint workspace (checkpoints, step buffer, channel adjoints), grown on demand
+  size_t adj_bytes = 0;
   int n_cu = 0;
 };
+constexpr long long kAdjMaxCheckpoints = 128;  // per ray slot; longer rays thin their checkpoints
 constexpr unsigned kCounterSlots = 1024;
 std::mutex g_scratch_mu;
 DeviceScratch g_scratch[64];
@@ -192,6 +195,118 @@ void free_model_memory(rt_model* m) {
   dev_free(m->raw_ne, m->raw_bytes);
   dev_free(m->raw_te, m->raw_bytes);
   m->nfg = nullptr; m->te = nullptr; m->raw_ne = nullptr; m->raw_te = nullptr;
+}
+
+
+unsigned* next_counters(DeviceScratch* sc) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  const unsigned slot = sc->next_slot++ % kCounterSlots;
+  return sc->counters + size_t(slot) * kXcds;
+}
+
+// Validation of a trace call (host only) and the parts of its launch plan that
+// the forward and the adjoint share: geometry, frequencies, image axes, stepping
+// controls and the per-pixel launch table.
+rt_status prepare_call(const rt_model* const* models, int32_t n_models, const double* freq_hz, int32_t n_freq,
+                       const rt_image_desc* image, const rt_params* params, hipStream_t s, TraceArgs& a,
+                       DeviceScratch** sc_out) {
+  if (!models || n_models < 1) return fail(RT_E_INVALID_ARG, "need at least one model");
+  if (!freq_hz || n_freq < 1) return fail(RT_E_INVALID_ARG, "need at least one frequency");
+  if (!image || !params) return fail(RT_E_INVALID_ARG, "image/params is NULL");
+  for (int k = 0; k < n_models; ++k)
+    if (!models[k]) return fail(RT_E_INVALID_ARG, "models[" + std::to_string(k) + "] is NULL");
+  const rt_model* m0 = models[0];
+  for (int k = 1; k < n_models; ++k) {
+    if (!same_grid(models[k]->desc, m0->desc)) return fail(RT_E_INVALID_ARG, "models must share one grid descriptor");
+    if (models[k]->device != m0->device) return fail(RT_E_INVALID_ARG, "models must be on one device");
+  }
+  for (int k = 0; k < n_freq; ++k)
+    if (!(std::isfinite(freq_hz[k]) && freq_hz[k] > 0.0)) return fail(RT_E_INVALID_ARG, "frequencies must be finite and > 0");
+  if (n_models > kMaxModels) return fail(RT_E_CAPACITY, "more than 16 models in one call");
+  if (n_freq > kMaxFreqs) return fail(RT_E_CAPACITY, "more than 128 frequencies in one call");
+  const rt_params& P = *params;
+  if (P.abi_version != RT_ABI_VERSION) return fail(RT_E_INVALID_ARG, "params->abi_version mismatch");
+  const uint32_t known = RT_USE_MAGNIFICATION | RT_USE_REFRACTION | RT_PREC_ALL_FP32 | RT_SCHED_PLAIN |
+                         RT_DETERMINISTIC_GRAD | RT_TEST_NO_ABSORPTION;
+  if (P.flags & ~known) return fail(RT_E_INVALID_ARG, "unknown flag bits");
+  if (!(std::isfinite(P.ds_max) && P.ds_max > 0.0)) return fail(RT_E_INVALID_ARG, "ds_max must be > 0");
+  if (!(std::isfinite(P.n_floor) && P.n_floor > 0.0 && P.n_floor <= 1.0)) return fail(RT_E_INVALID_ARG, "n_floor must be in (0, 1]");
+  if (P.max_steps < 1) return fail(RT_E_INVALID_ARG, "max_steps must be >= 1");
+  if (!(std::isfinite(P.perturb_ratio) && P.perturb_ratio > 0.0)) return fail(RT_E_INVALID_ARG, "perturb_ratio must be > 0");
+  if (!(std::isfinite(P.tb_inner_K) && std::isfinite(P.tb_sky_K))) return fail(RT_E_INVALID_ARG, "boundary temperatures must be finite");
+  const rt_image_desc& I = *image;
+  if (I.nu < 1 || I.nv < 1) return fail(RT_E_INVALID_ARG, "image needs nu, nv >= 1");
+  if (!(std::isfinite(I.half_u) && std::isfinite(I.half_v) && I.half_u > 0 && I.half_v > 0))
+    return fail(RT_E_INVALID_ARG, "image half widths must be > 0");
+  if (!finite3(I.obs_dir) || !finite3(I.up)) return fail(RT_E_INVALID_ARG, "obs_dir/up not finite");
+  double o[3] = {I.obs_dir[0], I.obs_dir[1], I.obs_dir[2]};
+  const double on = std::sqrt(o[0] * o[0] + o[1] * o[1] + o[2] * o[2]);
+  if (!(on > 0)) return fail(RT_E_INVALID_ARG, "obs_dir is zero");
+  for (double& x : o) x /= on;
+  double u[3] = {I.up[1] * o[2] - I.up[2] * o[1], I.up[2] * o[0] - I.up[0] * o[2], I.up[0] * o[1] - I.up[1] * o[0]};
+  const double un = std::sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+  if (!(un > 1e-12)) return fail(RT_E_INVALID_ARG, "up is parallel to obs_dir");
+  for (double& x : u) x /= un;
+  const double v[3] = {o[1] * u[2] - o[2] * u[1], o[2] * u[0] - o[0] * u[2], o[0] * u[1] - o[1] * u[0]};
+  const long long npx = (long long)I.nu * I.nv;
+  const long long total = npx * n_models * n_freq;
+  if (total > (1ll << 31) - 1) return fail(RT_E_CAPACITY, "more than 2^31-1 rays in one call");
+
+  rt_status st = hip_check(hipSetDevice(m0->device), "hipSetDevice");
+  if (st != RT_OK) return st;
+  DeviceScratch* sc = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    st = scratch_for(m0->device, &sc);
+    if (st != RT_OK) return st;
+    if (sc->start_cap < size_t(npx)) {
+      dev_free(sc->start_idx, sc->start_cap * 6 * sizeof(double));
+      sc->start_idx = nullptr;
+      sc->start_cap = 0;
+      st = dev_alloc((void**)&sc->start_idx, size_t(npx) * 6 * sizeof(double), "launch table");
+      if (st != RT_OK) return st;
+      sc->start_cap = size_t(npx);
+    }
+    const size_t nne = size_t(npx) * size_t(n_models);
+    if (sc->start_ne_cap < nne) {
+      dev_free(sc->start_ne, sc->start_ne_cap * sizeof(float));
+      sc->start_ne = nullptr;
+      sc->start_ne_cap = 0;
+      st = dev_alloc((void**)&sc->start_ne, nne * sizeof(float), "start n_e table");
+      if (st != RT_OK) return st;
+      sc->start_ne_cap = nne;
+    }
+  }
+  a.g = m0->geom;
+  for (int k = 0; k < n_models; ++k) a.models[k] = {models[k]->nfg, models[k]->te};
+  for (int k = 0; k < n_freq; ++k) {
+    a.freqs[k] = freq_hz[k];
+    a.xf[k] = (8.98e3 / freq_hz[k]) * (8.98e3 / freq_hz[k]);
+    a.lnf[k] = float(std::log(freq_hz[k]));
+  }
+  a.n_models = n_models;
+  a.n_freq = n_freq;
+  a.nu = I.nu; a.nv = I.nv;
+  a.tiles_u = (I.nu + kTile - 1) / kTile;
+  a.tiles_v = (I.nv + kTile - 1) / kTile;
+  a.tiles_per_image = a.tiles_u * a.tiles_v;
+  for (int k = 0; k < 3; ++k) { a.o[k] = o[k]; a.u[k] = u[k]; a.v[k] = v[k]; }
+  a.half_u = I.half_u; a.half_v = I.half_v;
+  a.ds_max = float(P.ds_max);
+  a.n_floor = float(P.n_floor);
+  a.ds_max_d = P.ds_max;
+  a.n_floor_d = P.n_floor;
+  a.eta = float(P.perturb_ratio);
+  a.max_steps = P.max_steps;
+  a.tb_inner = P.tb_inner_K;
+  a.tb_sky = P.tb_sky_K;
+  a.flags = P.flags;
+  a.launch = sc->start_idx;
+  a.launch_ne = sc->start_ne;
+  st = hip_check(launch_start_index(a, sc->start_idx, sc->start_ne, s), "start index");
+  if (st != RT_OK) return st;
+  *sc_out = sc;
+  return RT_OK;
 }
 
 }  // namespace
@@ -336,48 +451,13 @@ rt_status rt_trace_maps(const rt_model* const* models, int32_t n_models, const d
                         rt_trace_stats* stats_out, const int32_t* path_rays, int32_t n_path_rays,
                         int32_t path_capacity, float* path_out, int32_t* path_len_out, void* hip_stream) {
   try {
-    // ---- validation (host only) ----
-    if (!models || n_models < 1) return fail(RT_E_INVALID_ARG, "need at least one model");
-    if (!freq_hz || n_freq < 1) return fail(RT_E_INVALID_ARG, "need at least one frequency");
-    if (!image || !params || !tb_out) return fail(RT_E_INVALID_ARG, "image/params/tb_out is NULL");
-    for (int k = 0; k < n_models; ++k)
-      if (!models[k]) return fail(RT_E_INVALID_ARG, "models[" + std::to_string(k) + "] is NULL");
-    const rt_model* m0 = models[0];
-    for (int k = 1; k < n_models; ++k) {
-      if (!same_grid(models[k]->desc, m0->desc)) return fail(RT_E_INVALID_ARG, "models must share one grid descriptor");
-      if (models[k]->device != m0->device) return fail(RT_E_INVALID_ARG, "models must be on one device");
-    }
-    for (int k = 0; k < n_freq; ++k)
-      if (!(std::isfinite(freq_hz[k]) && freq_hz[k] > 0.0)) return fail(RT_E_INVALID_ARG, "frequencies must be finite and > 0");
-    if (n_models > kMaxModels) return fail(RT_E_CAPACITY, "more than 16 models in one call");
-    if (n_freq > kMaxFreqs) return fail(RT_E_CAPACITY, "more than 128 frequencies in one call");
-    const rt_params& P = *params;
-    if (P.abi_version != RT_ABI_VERSION) return fail(RT_E_INVALID_ARG, "params->abi_version mismatch");
-    const uint32_t known = RT_USE_MAGNIFICATION | RT_USE_REFRACTION | RT_PREC_ALL_FP32 | RT_SCHED_PLAIN |
-                           RT_DETERMINISTIC_GRAD | RT_TEST_NO_ABSORPTION;
-    if (P.flags & ~known) return fail(RT_E_INVALID_ARG, "unknown flag bits");
-    if (!(std::isfinite(P.ds_max) && P.ds_max > 0.0)) return fail(RT_E_INVALID_ARG, "ds_max must be > 0");
-    if (!(std::isfinite(P.n_floor) && P.n_floor > 0.0 && P.n_floor <= 1.0)) return fail(RT_E_INVALID_ARG, "n_floor must be in (0, 1]");
-    if (P.max_steps < 1) return fail(RT_E_INVALID_ARG, "max_steps must be >= 1");
-    if (!(std::isfinite(P.perturb_ratio) && P.perturb_ratio > 0.0)) return fail(RT_E_INVALID_ARG, "perturb_ratio must be > 0");
-    if (!(std::isfinite(P.tb_inner_K) && std::isfinite(P.tb_sky_K))) return fail(RT_E_INVALID_ARG, "boundary temperatures must be finite");
-    const rt_image_desc& I = *image;
-    if (I.nu < 1 || I.nv < 1) return fail(RT_E_INVALID_ARG, "image needs nu, nv >= 1");
-    if (!(std::isfinite(I.half_u) && std::isfinite(I.half_v) && I.half_u > 0 && I.half_v > 0))
-      return fail(RT_E_INVALID_ARG, "image half widths must be > 0");
-    if (!finite3(I.obs_dir) || !finite3(I.up)) return fail(RT_E_INVALID_ARG, "obs_dir/up not finite");
-    double o[3] = {I.obs_dir[0], I.obs_dir[1], I.obs_dir[2]};
-    const double on = std::sqrt(o[0] * o[0] + o[1] * o[1] + o[2] * o[2]);
-    if (!(on > 0)) return fail(RT_E_INVALID_ARG, "obs_dir is zero");
-    for (double& x : o) x /= on;
-    double u[3] = {I.up[1] * o[2] - I.up[2] * o[1], I.up[2] * o[0] - I.up[0] * o[2], I.up[0] * o[1] - I.up[1] * o[0]};
-    const double un = std::sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
-    if (!(un > 1e-12)) return fail(RT_E_INVALID_ARG, "up is parallel to obs_dir");
-    for (double& x : u) x /= un;
-    const double v[3] = {o[1] * u[2] - o[2] * u[1], o[2] * u[0] - o[0] * u[2], o[0] * u[1] - o[1] * u[0]};
-    const long long npx = (long long)I.nu * I.nv;
-    const long long total = npx * n_models * n_freq;
-    if (total > (1ll << 31) - 1) return fail(RT_E_CAPACITY, "more than 2^31-1 rays in one call");
+    if (!tb_out) return fail(RT_E_INVALID_ARG, "tb_out is NULL");
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    TraceArgs a{};
+    DeviceScratch* sc = nullptr;
+    rt_status st = prepare_call(models, n_models, freq_hz, n_freq, image, params, s, a, &sc);
+    if (st != RT_OK) return st;
+    const long long total = (long long)a.nu * a.nv * n_models * n_freq;
     if (n_path_rays < 0) return fail(RT_E_INVALID_ARG, "n_path_rays < 0");
     if (n_path_rays > 0) {
       if (!path_rays || !path_out || !path_len_out || path_capacity < 1)
@@ -386,72 +466,17 @@ rt_status rt_trace_maps(const rt_model* const* models, int32_t n_models, const d
         if (path_rays[k] < 0 || path_rays[k] >= total) return fail(RT_E_INVALID_ARG, "path ray index out of range");
         if (k > 0 && path_rays[k] <= path_rays[k - 1]) return fail(RT_E_INVALID_ARG, "path rays must be sorted and distinct");
       }
-    }
-
-    // ---- launch plan ----
-    hipStream_t s = static_cast<hipStream_t>(hip_stream);
-    rt_status st = hip_check(hipSetDevice(m0->device), "hipSetDevice");
-    if (st != RT_OK) return st;
-    DeviceScratch* sc = nullptr;
-    {
-      std::lock_guard<std::mutex> lk(g_scratch_mu);
-      st = scratch_for(m0->device, &sc);
-      if (st != RT_OK) return st;
-      if (sc->start_cap < size_t(npx)) {
-        dev_free(sc->start_idx, sc->start_cap * 6 * sizeof(double));
-        sc->start_idx = nullptr;
-        sc->start_cap = 0;
-        st = dev_alloc((void**)&sc->start_idx, size_t(npx) * 6 * sizeof(double), "launch table");
-        if (st != RT_OK) return st;
-        sc->start_cap = size_t(npx);
+      {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        if (sc->path_cap < size_t(n_path_rays)) {
+          dev_free(sc->path_rays, sc->path_cap * sizeof(int32_t));
+          sc->path_rays = nullptr;
+          sc->path_cap = 0;
+          st = dev_alloc((void**)&sc->path_rays, size_t(n_path_rays) * sizeof(int32_t), "path rays");
+          if (st != RT_OK) return st;
+          sc->path_cap = size_t(n_path_rays);
+        }
       }
-      const size_t nne = size_t(npx) * size_t(n_models);
-      if (sc->start_ne_cap < nne) {
-        dev_free(sc->start_ne, sc->start_ne_cap * sizeof(float));
-        sc->start_ne = nullptr;
-        sc->start_ne_cap = 0;
-        st = dev_alloc((void**)&sc->start_ne, nne * sizeof(float), "start n_e table");
-        if (st != RT_OK) return st;
-        sc->start_ne_cap = nne;
-      }
-      if (n_path_rays > 0 && sc->path_cap < size_t(n_path_rays)) {
-        dev_free(sc->path_rays, sc->path_cap * sizeof(int32_t));
-        sc->path_rays = nullptr;
-        sc->path_cap = 0;
-        st = dev_alloc((void**)&sc->path_rays, size_t(n_path_rays) * sizeof(int32_t), "path rays");
-        if (st != RT_OK) return st;
-        sc->path_cap = size_t(n_path_rays);
-      }
-    }
-    TraceArgs a{};
-    a.g = m0->geom;
-    for (int k = 0; k < n_models; ++k) a.models[k] = {models[k]->nfg, models[k]->te};
-    for (int k = 0; k < n_freq; ++k) {
-      a.freqs[k] = freq_hz[k];
-      a.xf[k] = (8.98e3 / freq_hz[k]) * (8.98e3 / freq_hz[k]);
-      a.lnf[k] = float(std::log(freq_hz[k]));
-    }
-    a.n_models = n_models;
-    a.n_freq = n_freq;
-    a.nu = I.nu; a.nv = I.nv;
-    a.tiles_u = (I.nu + kTile - 1) / kTile;
-    a.tiles_v = (I.nv + kTile - 1) / kTile;
-    a.tiles_per_image = a.tiles_u * a.tiles_v;
-    for (int k = 0; k < 3; ++k) { a.o[k] = o[k]; a.u[k] = u[k]; a.v[k] = v[k]; }
-    a.half_u = I.half_u; a.half_v = I.half_v;
-    a.ds_max = float(P.ds_max);
-    a.n_floor = float(P.n_floor);
-    a.ds_max_d = P.ds_max;
-    a.n_floor_d = P.n_floor;
-    a.eta = float(P.perturb_ratio);
-    a.max_steps = P.max_steps;
-    a.tb_inner = P.tb_inner_K;
-    a.tb_sky = P.tb_sky_K;
-    a.flags = P.flags;
-    a.tb = tb_out;
-    a.info = info_out;
-    a.stats = stats_out;
-    if (n_path_rays > 0) {
       st = hip_check(hipMemcpyAsync(sc->path_rays, path_rays, size_t(n_path_rays) * sizeof(int32_t),
                                     hipMemcpyHostToDevice, s), "copy path rays");
       if (st == RT_OK) st = hip_check(hipStreamSynchronize(s), "path rays sync");
@@ -462,14 +487,14 @@ rt_status rt_trace_maps(const rt_model* const* models, int32_t n_models, const d
       a.path_out = path_out;
       a.path_len = path_len_out;
     }
+    a.tb = tb_out;
+    a.info = info_out;
+    a.stats = stats_out;
     if (stats_out) {
       st = hip_check(launch_fill_u32(reinterpret_cast<unsigned*>(stats_out), 0u, sizeof(rt_trace_stats) / 4, s), "stats fill");
       if (st != RT_OK) return st;
     }
-    a.launch = sc->start_idx;
-    a.launch_ne = sc->start_ne;
-    st = hip_check(launch_start_index(a, sc->start_idx, sc->start_ne, s), "start index");
-    if (st != RT_OK) return st;
+    const rt_params& P = *params;
     const bool mixed = (P.flags & RT_PREC_ALL_FP32) == 0;
     if (P.flags & RT_SCHED_PLAIN) {
       const int waves = a.tiles_per_image;
@@ -481,12 +506,7 @@ rt_status rt_trace_maps(const rt_model* const* models, int32_t n_models, const d
           if (st != RT_OK) return st;
         }
     } else {
-      unsigned slot;
-      {
-        std::lock_guard<std::mutex> lk(g_scratch_mu);
-        slot = sc->next_slot++ % kCounterSlots;
-      }
-      a.counters = sc->counters + size_t(slot) * kXcds;
+      a.counters = next_counters(sc);
       a.refill_min_idle = 64;
       if (const char* e = std::getenv("RT_REFILL_MIN_IDLE")) {
         const int v = std::atoi(e);
@@ -518,9 +538,82 @@ rt_status rt_trace_maps(const rt_model* const* models, int32_t n_models, const d
 rt_status rt_trace_adjoint(const rt_model* model, const double* freq_hz, int32_t n_freq, const rt_image_desc* image,
                            const rt_params* params, const float* weights, double* loss_out, float* grad_ln_ne,
                            float* grad_ln_te, float* tb_out, void* hip_stream) {
-  (void)model; (void)freq_hz; (void)n_freq; (void)image; (void)params; (void)weights; (void)loss_out;
-  (void)grad_ln_ne; (void)grad_ln_te; (void)tb_out; (void)hip_stream;
-  return fail(RT_E_UNSUPPORTED, "adjoint not built yet");
+  try {
+    if (!model) return fail(RT_E_INVALID_ARG, "model is NULL");
+    if (!weights || !loss_out || !grad_ln_ne || !grad_ln_te)
+      return fail(RT_E_INVALID_ARG, "weights, loss_out, grad_ln_ne and grad_ln_te must not be NULL");
+    if (params && (params->flags & RT_PREC_ALL_FP32))
+      return fail(RT_E_UNSUPPORTED, "the adjoint runs in mixed precision only (RT_PREC_ALL_FP32 is not supported)");
+    if (params && (params->flags & RT_TEST_NO_ABSORPTION))
+      return fail(RT_E_UNSUPPORTED, "RT_TEST_NO_ABSORPTION is a forward-only test mode");
+    if (params && (params->flags & RT_DETERMINISTIC_GRAD))
+      return fail(RT_E_UNSUPPORTED, "RT_DETERMINISTIC_GRAD is not supported by this build");
+    if (params && params->checkpoint_every < 0) return fail(RT_E_INVALID_ARG, "checkpoint_every must be >= 0");
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    TraceArgs a{};
+    DeviceScratch* sc = nullptr;
+    const rt_model* models[1] = {model};
+    rt_status st = prepare_call(models, 1, freq_hz, n_freq, image, params, s, a, &sc);
+    if (st != RT_OK) return st;
+    const rt_params& P = *params;
+    const long long npx = (long long)a.nu * a.nv;
+    const int K = P.checkpoint_every > 0 ? P.checkpoint_every : 64;
+    long long cap = ((long long)P.max_steps + K - 1) / K + 1;
+    if (cap > kAdjMaxCheckpoints) cap = kAdjMaxCheckpoints;
+    if (cap < 2) cap = 2;
+    cap += cap & 1;  // even: thinning keeps every other checkpoint
+    const int n_tiles = a.tiles_per_image * n_freq;
+    long long blocks = (long long)sc->n_cu * adjoint_blocks_per_cu(a.g.kind);
+    const long long max_useful = (n_tiles + 3) / 4;
+    if (blocks > max_useful) blocks = max_useful;
+    if (blocks < 1) blocks = 1;
+    const long long n_slots = blocks * 256;
+    const size_t ck_bytes = size_t(cap) * kCkptFields * size_t(n_slots) * sizeof(double);
+    const size_t st_bytes = size_t(K) * kCkptFields * size_t(n_slots) * sizeof(double);
+    const long long nvp = (long long)a.g.n0 * a.g.n1 * a.g.n2p;
+    const size_t acc_bytes = size_t(nvp) * kGradChannels * sizeof(double);
+    const size_t tb_bytes = tb_out ? 0 : size_t(npx) * size_t(n_freq) * sizeof(float);
+    const size_t need = ck_bytes + st_bytes + acc_bytes + tb_bytes + 256 * 4;
+    char* ws = nullptr;
+    {
+      std::lock_guard<std::mutex> lk(g_scratch_mu);
+      if (sc->adj_bytes < need) {
+        dev_free(sc->adj_ws, sc->adj_bytes);
+        sc->adj_ws = nullptr;
+        sc->adj_bytes = 0;
+        st = dev_alloc((void**)&sc->adj_ws, need, "adjoint workspace");
+        if (st != RT_OK) return st;
+        sc->adj_bytes = need;
+      }
+      ws = static_cast<char*>(sc->adj_ws);
+    }
+    AdjointArgs aa{};
+    size_t off = 0;
+    aa.gacc = reinterpret_cast<double*>(ws + off); off += acc_bytes;
+    aa.ckpt = reinterpret_cast<double*>(ws + off); off += ck_bytes;
+    aa.steps = reinterpret_cast<double*>(ws + off); off += st_bytes;
+    float* tb = tb_out ? tb_out : reinterpret_cast<float*>(ws + off);
+    a.tb = tb;
+    a.info = nullptr;
+    a.stats = nullptr;
+    aa.t = a;
+    aa.weights = weights;
+    aa.loss = loss_out;
+    aa.counter = next_counters(sc);
+    aa.K = K;
+    aa.ckpt_cap = int(cap);
+    aa.n_slots = int(n_slots);
+    aa.n_tiles = n_tiles;
+    st = hip_check(launch_fill_u32(reinterpret_cast<unsigned*>(aa.gacc), 0u, (long long)(acc_bytes / 4), s), "gradient fill");
+    if (st == RT_OK) st = hip_check(launch_fill_u32(reinterpret_cast<unsigned*>(loss_out), 0u, 2, s), "loss fill");
+    if (st == RT_OK) st = hip_check(launch_fill_u32(aa.counter, 0u, 1, s), "counter fill");
+    if (st == RT_OK) st = hip_check(launch_adjoint(aa, int(blocks), s), "adjoint launch");
+    if (st == RT_OK)
+      st = hip_check(launch_unpack_grad(a.g, model->nfg, model->te, aa.gacc, grad_ln_ne, grad_ln_te, s), "gradient gather");
+    return st;
+  } catch (...) {
+    return fail(RT_E_INTERNAL, "unexpected exception");
+  }
 }
 
 }  // extern "C"

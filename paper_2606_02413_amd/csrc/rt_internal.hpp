@@ -64,6 +64,21 @@ struct TraceArgs {
   int refill_min_idle;        // a wave refills once at least this many lanes are idle (1..64)
 };
 
+// Reverse-mode (adjoint) launch over one model: the forward trace of every ray
+// with checkpoints, then its reverse sweep.
+constexpr int kCkptFields = 10;   // r (3), p (3), grid index (3), optical depth so far
+constexpr int kGradChannels = 5;  // per vertex: n_e, the three index-space gradient channels, T
+struct AdjointArgs {
+  TraceArgs t;                // one model, image layout [freq][nv][nu]
+  const float* weights;       // [n_freq][nv][nu]
+  double* loss;               // device scalar, accumulated
+  double* gacc;               // [n0 * n1 * n2p][kGradChannels] channel adjoints, zeroed before launch
+  double* ckpt;               // [ckpt_cap][kCkptFields][n_slots]
+  double* steps;              // [K][kCkptFields][n_slots]
+  unsigned* counter;          // tile claim counter, zeroed before launch
+  int K, ckpt_cap, n_slots, n_tiles;
+};
+
 // Launchers (rt_kernels.hip).
 hipError_t launch_pack(const DevGeom& g, const float* ne, const float* te, float4* nfg, float* te_out,
                        hipStream_t s);
@@ -73,7 +88,14 @@ hipError_t launch_trace(const TraceArgs& a, bool plain, bool mixed, int grid_blo
 hipError_t launch_start_index(const TraceArgs& a, double* out, float* ne_out, hipStream_t s);
 int persistent_blocks_per_cu(bool mixed, int kind);
 
+// Launchers (rt_adjoint.hip).
+hipError_t launch_adjoint(const AdjointArgs& a, int blocks, hipStream_t s);
+hipError_t launch_unpack_grad(const DevGeom& g, const float4* nfg, const float* te, const double* gacc,
+                              float* grad_ln_ne, float* grad_ln_te, hipStream_t s);
+int adjoint_blocks_per_cu(int kind);
+
 }  // namespace rt
 
 static_assert(sizeof(rt_ray_info) == 32, "rt_ray_info is 32 bytes");
 static_assert(sizeof(rt_trace_stats) == 40, "rt_trace_stats is 40 bytes");
+static_assert(sizeof(rt::AdjointArgs) <= 4096, "kernel arguments fit the 4 KiB argument segment");

@@ -219,17 +219,19 @@ struct Loc {
   // chain-rule pieces at the evaluation point (spherical)
   float rinv, rhoinv, rho, x, y, z;
   bool axis;
+  bool cl0, cl1, cl2;  // index held at an edge along axis 0, 1, 2 (no dependence on position)
 };
 
 // Cell of a clamped axis from (integer base, FP32 index offset): a in [0, n-2],
 // u in [0, 1]; beyond an edge the index is held at the edge.
-__device__ __forceinline__ void cell_clamped(float x, int I, int n, int& a, float& u) {
+__device__ __forceinline__ void cell_clamped(float x, int I, int n, int& a, float& u, bool& held) {
   float fk = floorf(x);
   if (!(fk >= -1.0e9f && fk <= 1.0e9f)) fk = 0.0f;  // NaN guard keeps every gather in bounds
   u = x - fk;
   a = I + int(fk);
-  if (a < 0) { a = 0; u = 0.0f; }
-  else if (a > n - 2) { a = n - 2; u = 1.0f; }
+  held = false;
+  if (a < 0) { a = 0; u = 0.0f; held = true; }
+  else if (a > n - 2) { a = n - 2; u = 1.0f; held = true; }
 }
 
 __device__ __forceinline__ void cell_periodic(float x, int I, int n, int& c, float& w) {
@@ -270,10 +272,11 @@ __device__ __forceinline__ void locate(const DevGeom& g, const StepOrigin& O, fl
     x2 = O.f2 + dz * g.inv_sp[2];
   }
   int a, b, c;
-  cell_clamped(x0, O.i0, g.n0, a, L.u);
-  cell_clamped(x1, O.i1, g.n1, b, L.v);
+  cell_clamped(x0, O.i0, g.n0, a, L.u, L.cl0);
+  cell_clamped(x1, O.i1, g.n1, b, L.v, L.cl1);
+  L.cl2 = false;
   if constexpr (KIND == RT_GRID_SPHERICAL_LOGR) cell_periodic(x2, O.i2, g.n2, c, L.w);
-  else cell_clamped(x2, O.i2, g.n2, c, L.w);
+  else cell_clamped(x2, O.i2, g.n2, c, L.w, L.cl2);
   L.key = (a * g.n1 + b) * g.n2p + c;
 }
 
@@ -561,14 +564,17 @@ __device__ __forceinline__ float segment_phi(float x) {
   return (1.0f - __builtin_amdgcn_exp2f(-1.44269504089f * x)) / x;
 }
 
+// Tracing mode of ray_step: from the call's flags, or fixed at compile time.
+enum : int { kModeFlags = 0, kModeLos = 1, kModeNoMag = 2, kModeFull = 3 };
+
 // One central RK4 step with its two perturbed retraces, termination test and
 // transfer segment.  Returns the termination code (kRunning to continue); on
 // termination R holds the end point, the code and the last-step fraction.
-template <bool MIXED, int KIND>
+template <bool MIXED, int KIND, int MODE = kModeFlags>
 __device__ int ray_step(const TraceArgs& a, RayState& R, CellCache& C) {
   using Real = typename RealOf<MIXED>::T;
-  const bool refr = (a.flags & RT_USE_REFRACTION) != 0;
-  const bool mag = refr && (a.flags & RT_USE_MAGNIFICATION) != 0;
+  const bool refr = (MODE == kModeFlags) ? (a.flags & RT_USE_REFRACTION) != 0 : (MODE != kModeLos);
+  const bool mag = (MODE == kModeFlags) ? refr && (a.flags & RT_USE_MAGNIFICATION) != 0 : (MODE == kModeFull);
 
   // All evaluation points of this step are r_i + (FP32 offset).
   StepOrigin O;

@@ -231,6 +231,78 @@ def trace_maps(models, freqs, image, prm, *, info=True, stats=True, path_rays=No
     return res
 
 
+def trace_adjoint(model, freqs, image, prm, weights, *, tb=True, stream=None, out=None):
+    """Reverse mode of the forward maps of one model: loss = sum w T_b and its
+    gradient w.r.t. ln n_e and ln T of every vertex.  `weights` is a float32
+    device tensor [F][nv][nu].  Returns a dict of device tensors: loss (float64
+    [1]), grad_ln_ne and grad_ln_te (float32, grid shape), tb [F][nv][nu] when
+    `tb` is true."""
+    import torch
+    freqs = np.ascontiguousarray(np.atleast_1d(freqs), dtype=np.float64)
+    F = freqs.shape[0]
+    dev = torch.device("cuda", model.device)
+    if tuple(weights.shape) != (F, image.nv, image.nu) or weights.dtype != torch.float32:
+        raise ValueError("weights must be float32 [n_freq][nv][nu]")
+    if not weights.is_contiguous():
+        raise ValueError("weights must be contiguous")
+    res = {} if out is None else out
+    if "loss" not in res:
+        res["loss"] = torch.empty(1, dtype=torch.float64, device=dev)
+    if "grad_ln_ne" not in res:
+        res["grad_ln_ne"] = torch.empty(model.shape, dtype=torch.float32, device=dev)
+    if "grad_ln_te" not in res:
+        res["grad_ln_te"] = torch.empty(model.shape, dtype=torch.float32, device=dev)
+    if tb and "tb" not in res:
+        res["tb"] = torch.empty((F, image.nv, image.nu), dtype=torch.float32, device=dev)
+    ptr = lambda k: C.c_void_p(res[k].data_ptr())
+    _check(lib().rt_trace_adjoint(model.handle, freqs.ctypes.data_as(C.POINTER(C.c_double)), F, C.byref(image),
+                                  C.byref(prm), C.c_void_p(weights.data_ptr()), ptr("loss"), ptr("grad_ln_ne"),
+                                  ptr("grad_ln_te"), ptr("tb") if tb else C.c_void_p(0), _stream_ptr(stream)))
+    return res
+
+
+def _make_function():
+    import torch
+
+    class RTSunFunction(torch.autograd.Function):
+        """T_b maps of one model as a differentiable function of (ln n_e, ln T).
+
+        forward: n_e = exp(ln n_e), T = exp(ln T) replace the model's values
+        (rt_model_update), then rt_trace_maps; backward: rt_trace_adjoint with the
+        incoming gradient of the maps as the loss weights."""
+
+        @staticmethod
+        def forward(ctx, ln_ne, ln_te, model, freqs, image, prm):
+            ne = torch.exp(ln_ne.detach()).to(torch.float32).contiguous()
+            te = torch.exp(ln_te.detach()).to(torch.float32).contiguous()
+            model.update_device(ne, te)
+            out = trace_maps([model], freqs, image, prm, info=False, stats=False)
+            ctx.save_for_backward(ne, te)
+            ctx.model, ctx.freqs, ctx.image, ctx.prm = model, freqs, image, prm
+            return out["tb"][0]
+
+        @staticmethod
+        def backward(ctx, grad_tb):
+            ne, te = ctx.saved_tensors
+            ctx.model.update_device(ne, te)  # the model may have been changed since the forward
+            w = grad_tb.detach().to(torch.float32).contiguous()
+            res = trace_adjoint(ctx.model, ctx.freqs, ctx.image, ctx.prm, w, tb=False)
+            return res["grad_ln_ne"], res["grad_ln_te"], None, None, None, None
+
+    return RTSunFunction
+
+
+_function = None
+
+
+def rtsun_function():
+    """The torch.autograd.Function over the library (created on first use)."""
+    global _function
+    if _function is None:
+        _function = _make_function()
+    return _function
+
+
 def decode_info(info_t):
     """Device uint8 [..., 32] tensor -> numpy structured array of INFO_DTYPE."""
     a = info_t.detach().cpu().numpy()
