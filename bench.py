@@ -63,10 +63,18 @@ def parse():
     ap.add_argument("--no-plain", action="store_true", help="skip the plain per-frequency timing")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint / forward timing")
+    ap.add_argument("--batching", action="store_true",
+                    help="only run the batching study (batched vs plain on the 4-model 64-frequency workload)")
+    ap.add_argument("--precision", action="store_true",
+                    help="only run the precision study (mixed vs all-FP32 vs oracle on the 512x256x512 workload)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (reference for HBM byte counters)")
     return ap.parse_args()
+
+
+def progress(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def calibrate_copy():
@@ -141,10 +149,162 @@ def adjoint_ratio(R, torch, model, stream, reps=2):
             "loss": float(adj["loss"].cpu()[0])}
 
 
+def precision_study(n_pixels=4096, seconds_note=True):
+    """Mixed precision vs all-FP32 vs the FP64 oracle on the precision workload:
+    512x256x512 model (r 1-30, 32 active regions, seed 4), 2048^2 image over
+    +/-3 R_sun, 16 frequencies 40-800 MHz; the oracle traces 4096 pixels drawn
+    with seed 3000 at every frequency (rays it flags as grazing, marginal or
+    polar are counted and left out of the error statistics).  Prints one JSON
+    line with the per-map max / median relative error of both variants."""
+    import torch
+    from oracle import oracle as O
+    from paper_2606_02413_amd import corona, rtsun as R
+    wl = corona.workload("precision")
+    t0 = time.perf_counter()
+    cor = wl.models(device="cuda")[0]
+    t_model = time.perf_counter() - t0
+    progress(f"precision model generated in {t_model:.0f} s")
+    model = R.Model.from_corona(cor)
+    im = R.image_desc(wl.n_pix, wl.half_width)
+    pix = corona.seeded_pixels(wl.n_pix, n_pixels, 3000)
+    pix_t = torch.from_numpy(pix.astype(np.int64)).cuda()
+    res = {}
+    for name, fp32 in (("mixed", False), ("all_fp32", True)):
+        prm = R.params(ds_max=wl.ds_max, n_floor=wl.n_floor, max_steps=wl.max_steps, all_fp32=fp32)
+        out = R.trace_maps([model], wl.freqs, im, prm, info=False, stats=True)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        R.trace_maps([model], wl.freqs, im, prm, info=False, stats=True, out=out)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        progress(f"precision {name}: {ms:.0f} ms")
+        steps = int(R.decode_stats(out["stats"])["ray_steps"])
+        tb = out["tb"][0].reshape(len(wl.freqs), -1)[:, pix_t].double().cpu().numpy()
+        res[name] = {"tb": tb, "ms": ms, "ray_steps": steps}
+        del out
+        torch.cuda.empty_cache()
+    med = O.OracleMedium.from_corona(cor)
+    P = O.make_params(ds_max=wl.ds_max, n_floor=wl.n_floor, max_steps=wl.max_steps, twin_check=True)
+    imo = O.make_image(wl.n_pix, wl.half_width)
+    t1 = time.perf_counter()
+    maps = []
+    for k, f in enumerate(wl.freqs):
+        o = O.trace_pixels(med, P, imo, f, pix.astype(np.int32))
+        progress(f"precision oracle {f / 1e6:.1f} MHz done")
+        ok = o["flags"] == 0
+        row = {"freq_MHz": round(f / 1e6, 3), "flagged": int((~ok).sum())}
+        for name in ("mixed", "all_fp32"):
+            rel = np.abs(res[name]["tb"][k] - o["tb"]) / np.maximum(np.abs(o["tb"]), 1.0)
+            row[name + "_max_rel"] = float(rel[ok].max())
+            row[name + "_median_rel"] = float(np.median(rel[ok]))
+            row[name + "_max_rel_all_rays"] = float(rel.max())
+            row[name + "_over_1e-3_all_rays"] = int((rel > 1e-3).sum())
+        maps.append(row)
+    t_orc = time.perf_counter() - t1
+    line = {"study": "precision", "workload": "512x256x512 model (r 1-30 R_sun, 32 active regions, seed 4), "
+            "2048^2 image +/-3 R_sun, 16 freq 40-800 MHz, ds_max 0.01, n_floor 0.1",
+            "oracle_pixels": f"{n_pixels} seeded (seed 3000) x 16 freq", "maps": maps,
+            "worst_mixed_max_rel": max(m["mixed_max_rel"] for m in maps),
+            "worst_all_fp32_max_rel": max(m["all_fp32_max_rel"] for m in maps),
+            "mixed": {"ms": res["mixed"]["ms"], "ray_steps_per_s": res["mixed"]["ray_steps"] / res["mixed"]["ms"] * 1e3},
+            "all_fp32": {"ms": res["all_fp32"]["ms"],
+                         "ray_steps_per_s": res["all_fp32"]["ray_steps"] / res["all_fp32"]["ms"] * 1e3},
+            "model_generation_s": t_model, "oracle_s": t_orc, "oracle_threads": O.default_threads()}
+    print(json.dumps(line), flush=True)
+    model.close()
+
+
+def batching_study():
+    """Batched (one persistent launch over every model, frequency and tile) vs
+    plain (one launch per image) on (a) the batched workload: the structured
+    model with seeds 0-3, 64 frequencies 40-800 MHz, 1024^2 image over +/-3 R_sun;
+    (b) a long-span variant: the spherically symmetric 64x32x64 model (r 1-3),
+    64 frequencies, 1024^2 image over +/-2.5 R_sun, ds_max 0.005, n_floor 1, whose
+    rays take 63 to ~1,100 steps.  (b) is also run with several refill thresholds."""
+    import torch
+    from paper_2606_02413_amd import corona, rtsun as R
+    stream = torch.cuda.current_stream()
+
+    def timed(fn):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1)
+
+    out = {"study": "batching"}
+    wl = corona.workload("batched")
+    models = [R.Model.from_corona(c) for c in wl.models(device="cuda")]
+    progress("batched workload models loaded")
+    im = R.image_desc(wl.n_pix, wl.half_width)
+    kw = dict(ds_max=wl.ds_max, n_floor=wl.n_floor, max_steps=wl.max_steps)
+    # a pass takes minutes, so each path is timed once, without a warm-up pass
+    # (allocation of the library's per-call tables is milliseconds)
+    res = {}
+    b_ms = timed(lambda: R.trace_maps(models, wl.freqs, im, R.params(**kw), info=False, stats=True, out=res))
+    steps = int(R.decode_stats(res["stats"])["ray_steps"])
+    progress(f"batched {b_ms:.0f} ms")
+    p_ms = 0.0
+    tb_b = res["tb"]
+    same = True
+    for k, mdl in enumerate(models):  # plain: 64 launches per model, timed per model
+        r1 = {}
+        p_ms += timed(lambda: R.trace_maps([mdl], wl.freqs, im, R.params(plain=True, **kw), info=False,
+                                           stats=False, out=r1))
+        same = same and bool(torch.equal(r1["tb"][0], tb_b[k]))
+        progress(f"plain model {k}: cumulative {p_ms:.0f} ms")
+        del r1
+    out["batched_workload"] = {"rays": int(tb_b.numel()), "ray_steps": steps, "batched_ms": b_ms, "plain_ms": p_ms,
+                               "batched_over_plain": p_ms / b_ms, "ray_steps_per_s_batched": steps / b_ms * 1e3,
+                               "rays_per_s_batched": tb_b.numel() / b_ms * 1e3, "bitwise_equal": same}
+    for m in models:
+        m.close()
+    del res, tb_b
+    torch.cuda.empty_cache()
+    # (b) long-span variant
+    cor = corona.spherically_symmetric()
+    mdl = R.Model.from_corona(cor)
+    freqs = corona.log_freqs(64)
+    im = R.image_desc(1024, 2.5)
+    kw = dict(ds_max=0.005, n_floor=1.0, max_steps=200000)
+    r1 = R.trace_maps([mdl], freqs, im, R.params(plain=True, **kw), info=False, stats=True)
+    torch.cuda.synchronize()
+    p_ms = timed(lambda: R.trace_maps([mdl], freqs, im, R.params(plain=True, **kw), info=False, stats=True, out=r1))
+    steps = int(R.decode_stats(r1["stats"])["ray_steps"])
+    st = R.decode_stats(r1["stats"])
+    span = {"plain_ms": p_ms, "ray_steps": steps, "max_steps": int(st["max_steps"]),
+            "mean_steps_per_traced_ray": steps / max(1, int(r1["tb"].numel()) - int(st["code_count"][3]))}
+    for thr in (64, 32, 8, 1):
+        os.environ["RT_REFILL_MIN_IDLE"] = str(thr)
+        r2 = R.trace_maps([mdl], freqs, im, R.params(**kw), info=False, stats=False)
+        torch.cuda.synchronize()
+        ms = timed(lambda: R.trace_maps([mdl], freqs, im, R.params(**kw), info=False, stats=False, out=r2))
+        span[f"batched_ms_refill{thr}"] = ms
+        span[f"batched_over_plain_refill{thr}"] = p_ms / ms
+        span[f"bitwise_equal_refill{thr}"] = bool(torch.equal(r2["tb"], r1["tb"]))
+        progress(f"long-span refill {thr}: {ms:.0f} ms (plain {p_ms:.0f})")
+        del r2
+    os.environ.pop("RT_REFILL_MIN_IDLE", None)
+    out["long_span_variant"] = span
+    print(json.dumps(out), flush=True)
+    mdl.close()
+
+
 def main():
     args = parse()
     if args.calibrate_copy:
         calibrate_copy()
+        return
+    if args.precision:
+        precision_study()
+        return
+    if args.batching:
+        batching_study()
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); this build has no multi-GPU path",

@@ -167,3 +167,29 @@ def test_all_fp32_variant_close(R, orc, structured_small):
     rel = np.abs(g["tb"].reshape(-1) - o["tb"]) / np.maximum(o["tb"], 1.0)
     print("all-fp32 max rel", rel[ok].max(), "median", np.median(rel[ok]))
     assert rel[ok].max() < 5e-2
+
+
+def test_structured_workload_full_size_sampled(R, orc):
+    """The benchmark workload at full size in the launch bench.py times: the
+    256x128x256 structured model (r 1-30), one persistent launch over the
+    512^2 x 8-frequency stack (40-800 MHz), ds_max 0.01, n_floor 0.1; the oracle
+    on 48 seeded pixels per frequency."""
+    import torch
+    wl = corona.workload("structured")
+    cor = wl.models(device="cuda")[0]
+    m = R.Model.from_corona(cor)
+    kw = PU.step_kwargs(wl.ds_max, wl.n_floor, max_steps=wl.max_steps)
+    print("case structured full size, persistent", flush=True)
+    g = PU.gpu_trace([m], wl.freqs, wl.n_pix, wl.half_width, kw)
+    st = g["stats"]
+    assert st["ray_steps"] == int(g["info"]["n_steps"].sum())
+    pix = corona.seeded_pixels(wl.n_pix, 48, 3001)
+    flagged = 0
+    for k, f in enumerate(wl.freqs):
+        o = PU.oracle_trace(orc, cor, f, wl.n_pix, wl.half_width, pix, kw)
+        s = PU.compare(g["tb"][0, k].reshape(-1)[pix], g["info"][0, k].reshape(-1)[pix], o,
+                       label=f"full-{f/1e6:.0f}MHz")
+        flagged += s["flagged"]
+    assert flagged < 0.1 * len(pix) * len(wl.freqs)
+    m.close()
+    torch.cuda.empty_cache()
