@@ -63,6 +63,8 @@ def parse():
     ap.add_argument("--no-plain", action="store_true", help="skip the plain per-frequency timing")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint / forward timing")
+    ap.add_argument("--adjoint-only", action="store_true",
+                    help="only run the adjoint / forward timing on the adjoint workload (for profiling)")
     ap.add_argument("--batching", action="store_true",
                     help="only run the batching study (batched vs plain on the 4-model 64-frequency workload)")
     ap.add_argument("--precision", action="store_true",
@@ -305,6 +307,14 @@ def main():
         return
     if args.batching:
         batching_study()
+        return
+    if args.adjoint_only:
+        import torch
+        from paper_2606_02413_amd import corona, rtsun as R
+        cor = corona.workload("adjoint").models(device="cuda")[0]
+        model = R.Model.from_corona(cor)
+        print(json.dumps({"adjoint": adjoint_ratio(R, torch, model, torch.cuda.current_stream(), reps=1)}), flush=True)
+        model.close()
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); this build has no multi-GPU path",

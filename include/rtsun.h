@@ -197,11 +197,13 @@ rt_status rt_trace_maps(const rt_model* const* models, int32_t n_models, const d
  * Each ray is traced forward with its state checkpointed every
  * params->checkpoint_every steps (0 selects 64); a ray longer than 128
  * checkpoints doubles its interval.  The reverse sweep recomputes each chunk of
- * steps from its checkpoint.  Channel adjoints are accumulated per lane and cell
+ * steps from its checkpoint, recording every step's start state and the model
+ * values its adjoint needs (188 bytes a step), and then sweeps the chunk
+ * backward from that record.  Channel adjoints are accumulated per lane and cell
  * in FP32 and added into an FP64 per-vertex accumulator with atomics, so the
  * last bits can vary between runs.  Mixed precision only: RT_PREC_ALL_FP32,
  * RT_DETERMINISTIC_GRAD and RT_TEST_NO_ABSORPTION return RT_E_UNSUPPORTED.  The library keeps a
- * per-device workspace (checkpoints, step buffer, accumulator), grown on demand.
+ * per-device workspace (checkpoints, chunk record, accumulator), grown on demand.
  * Errors: RT_E_INVALID_ARG for NULL or inconsistent arguments, RT_E_CAPACITY,
  * RT_E_OUT_OF_MEMORY, RT_E_DEVICE; nothing is written on a validation error. */
 rt_status rt_trace_adjoint(const rt_model* model, const double* freq_hz, int32_t n_freq,

@@ -18,6 +18,7 @@ __global__ __launch_bounds__(256, 1) void k_adjoint(AdjointArgs aa) {
   __shared__ float4 lds_c[4][8][kWaveLanes];
   __shared__ float lds_t[4][8][kWaveLanes];
   __shared__ float lds_g[4][8 * kGradChannels][kWaveLanes];
+  __shared__ float lds_log[4][kLogEntries * kLogWords][kWaveLanes];
   const TraceArgs& a = aa.t;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int slot = blockIdx.x * blockDim.x + threadIdx.x;
@@ -29,6 +30,7 @@ __global__ __launch_bounds__(256, 1) void k_adjoint(AdjointArgs aa) {
   A.key = -1;
   A.v = &lds_g[wave][0][lane];
   for (int k = 0; k < 8 * kGradChannels; ++k) A.v[k * kWaveLanes] = 0.0f;
+  float* lg = &lds_log[wave][0][lane];
   double loss = 0.0;
   for (;;) {
     unsigned t = 0;
@@ -39,7 +41,7 @@ __global__ __launch_bounds__(256, 1) void k_adjoint(AdjointArgs aa) {
     const int rem = int(t) - img * a.tiles_per_image;
     const int ty = rem / a.tiles_u, tx = rem - (rem / a.tiles_u) * a.tiles_u;
     const int i = ty * kTile + (lane >> 3), j = tx * kTile + (lane & 7);
-    if (i < a.nv && j < a.nu) adjoint_ray<KIND, MODE>(aa, img, i * a.nu + j, slot, C, A, loss);
+    if (i < a.nv && j < a.nu) adjoint_ray<KIND, MODE>(aa, img, i * a.nu + j, slot, C, A, lg, loss);
   }
   grad_flush(a.g, A, aa.gacc);
 #pragma unroll

@@ -27,41 +27,110 @@
 namespace rt {
 
 // ---------------------------------------------------------------------------
-// Channel-adjoint accumulator: one cell per lane, in LDS, channel ch of corner k
-// at v[(kGradChannels k + ch) * kWaveLanes]; flushed with FP64 atomics into the
-// per-vertex accumulator when the lane moves to another cell.
+// Channel adjoints.  A model evaluation's adjoint is first written to a per-lane
+// log entry (cell key, cell fractions, one adjoint per channel); after a run of
+// evaluations the log is replayed: entries of one cell are summed per corner in
+// registers and added to the lane's cell accumulator in LDS (channel ch of
+// corner k at v[(kGradChannels k + ch) * kWaveLanes]), which is flushed with
+// FP64 atomics into the per-vertex accumulator when the lane moves to another
+// cell.
 // ---------------------------------------------------------------------------
 struct GradAcc {
   int key;   // packed index of the cell's corner 0, or -1 when empty
   float* v;
 };
 
-__device__ __forceinline__ void grad_flush(const DevGeom& g, GradAcc& A, double* gacc) {
-  if (A.key < 0) return;
-  const int s1 = g.n2p, s0 = g.n1 * g.n2p;
-  // a key always names a cell whose far corner lies inside the packed grid
-  const bool inside = (long long)A.key + s0 + s1 + 1 < (long long)g.n0 * s0;
-#pragma unroll 1
-  for (int k = 0; k < 8; ++k) {
-    const int off = ((k & 4) ? s0 : 0) + ((k & 2) ? s1 : 0) + (k & 1);
-    double* dst = gacc + size_t(A.key + off) * kGradChannels;
-#pragma unroll
-    for (int ch = 0; ch < kGradChannels; ++ch) {
-      float* x = A.v + (k * kGradChannels + ch) * kWaveLanes;
-      const float val = *x;
-      if (val != 0.0f) {
-        if (inside) unsafeAtomicAdd(dst + ch, double(val));
-        *x = 0.0f;
-      }
-    }
-  }
-  A.key = -1;
+constexpr int kLogWords = 4 + kGradChannels;  // key, u, v, w, channel adjoints
+constexpr int kLogEntries = 7;                // evaluations logged before a replay
+
+// Write entry e: word j at lg[(kLogWords e + j) * kWaveLanes].
+__device__ __forceinline__ void log_entry(float* lg, int e, const Loc& L, float c0, float c1, float c2, float c3,
+                                          float c4) {
+  float* p = lg + e * kLogWords * kWaveLanes;
+  p[0] = __int_as_float(L.key);
+  p[kWaveLanes] = L.u; p[2 * kWaveLanes] = L.v; p[3 * kWaveLanes] = L.w;
+  p[4 * kWaveLanes] = c0; p[5 * kWaveLanes] = c1; p[6 * kWaveLanes] = c2;
+  p[7 * kWaveLanes] = c3; p[8 * kWaveLanes] = c4;
 }
 
-__device__ __forceinline__ void grad_select(const DevGeom& g, GradAcc& A, double* gacc, int key) {
-  if (A.key == key) return;
-  grad_flush(g, A, gacc);
+// Move the lane's LDS accumulator to cell `key`: the old cell's nonzero channel
+// adjoints go to gacc with FP64 atomics and the new cell starts from s.
+__device__ __forceinline__ void acc_replace(const DevGeom& g, GradAcc& A, double* gacc, int key,
+                                            const float s[8][kGradChannels]) {
+  if (A.key >= 0) {
+    const int s1 = g.n2p, s0 = g.n1 * g.n2p;
+    // a key always names a cell whose far corner lies inside the packed grid
+    const bool inside = (long long)A.key + s0 + s1 + 1 < (long long)g.n0 * s0;
+    float old[8][kGradChannels];
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+#pragma unroll
+      for (int ch = 0; ch < kGradChannels; ++ch) old[k][ch] = A.v[(k * kGradChannels + ch) * kWaveLanes];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int off = ((k & 4) ? s0 : 0) + ((k & 2) ? s1 : 0) + (k & 1);
+      double* dst = gacc + size_t(A.key + off) * kGradChannels;
+#pragma unroll
+      for (int ch = 0; ch < kGradChannels; ++ch)
+        if (inside && old[k][ch] != 0.0f) unsafeAtomicAdd(dst + ch, double(old[k][ch]));
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 8; ++k)
+#pragma unroll
+    for (int ch = 0; ch < kGradChannels; ++ch) A.v[(k * kGradChannels + ch) * kWaveLanes] = s[k][ch];
   A.key = key;
+}
+
+__device__ __forceinline__ void acc_commit(const DevGeom& g, GradAcc& A, double* gacc, int key,
+                                           const float s[8][kGradChannels]) {
+  if (key == A.key) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+#pragma unroll
+      for (int ch = 0; ch < kGradChannels; ++ch) A.v[(k * kGradChannels + ch) * kWaveLanes] += s[k][ch];
+  } else {
+    acc_replace(g, A, gacc, key, s);
+  }
+}
+
+// Replay log entries [0, n): consecutive entries of one cell are summed in
+// registers and committed to the accumulator once.
+__device__ __forceinline__ void log_replay(const DevGeom& g, GradAcc& A, double* gacc, const float* lg, int n) {
+  float s[8][kGradChannels];
+  int gk = -1;
+#pragma unroll 1
+  for (int e = 0; e < n; ++e) {
+    const float* p = lg + e * kLogWords * kWaveLanes;
+    const int key = __float_as_int(p[0]);
+    if (key != gk) {
+      if (gk >= 0) acc_commit(g, A, gacc, gk, s);
+      gk = key;
+#pragma unroll
+      for (int k = 0; k < 8; ++k)
+#pragma unroll
+        for (int ch = 0; ch < kGradChannels; ++ch) s[k][ch] = 0.0f;
+    }
+    float W[8];
+    weights8(p[kWaveLanes], p[2 * kWaveLanes], p[3 * kWaveLanes], W);
+#pragma unroll
+    for (int ch = 0; ch < kGradChannels; ++ch) {
+      const float c = p[(4 + ch) * kWaveLanes];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) s[k][ch] = fmaf(W[k], c, s[k][ch]);
+    }
+  }
+  if (gk >= 0) acc_commit(g, A, gacc, gk, s);
+}
+
+// Flush the accumulator to gacc (end of the lane's work).
+__device__ __forceinline__ void grad_flush(const DevGeom& g, GradAcc& A, double* gacc) {
+  float z[8][kGradChannels];
+#pragma unroll
+  for (int k = 0; k < 8; ++k)
+#pragma unroll
+    for (int ch = 0; ch < kGradChannels; ++ch) z[k][ch] = 0.0f;
+  acc_replace(g, A, gacc, -1, z);
 }
 
 // Trilinear interpolant of 4 channels over one cell and its derivatives along
@@ -119,23 +188,22 @@ __device__ __forceinline__ void sph_frame(const DevGeom& g, const Loc& L, SphFra
   F.cot = L.axis ? 0.0f : L.z * L.rhoinv;
 }
 
-// Adjoint of eval_grad at r_i + d: (n_b, g_b) -> position adjoint q, channel scatter.
-template <int KIND>
-__device__ __forceinline__ void eval_grad_adj(const DevGeom& g, const RayState& R, CellCache& C, GradAcc& A,
-                                              double* gacc, const StepOrigin& O, float dx, float dy, float dz,
-                                              float gbx, float gby, float gbz, float nb, float& qx, float& qy,
-                                              float& qz) {
+// Adjoint of eval_grad at r_i + d: (n_b, g_b) -> position adjoint q; the
+// channel adjoints go to log entry e.
+// WITH_N: the evaluation's n_e value has an adjoint (the step rule's stage-1
+// value); the other evaluations only feed forces and leave that channel alone.
+template <int KIND, bool WITH_N = false>
+__device__ __forceinline__ void eval_grad_adj(const DevGeom& g, const RayState& R, CellCache& C, float* lg, int e,
+                                              const StepOrigin& O, float dx, float dy, float dz, float gbx, float gby,
+                                              float gbz, float nb, float& qx, float& qy, float& qz) {
   Loc L;
   locate<KIND>(g, O, dx, dy, dz, L);
   ensure_cell(g, R.nfg, R.te, C, L.key);
-  grad_select(g, A, gacc, L.key);
   float4 q[8];
 #pragma unroll
   for (int k = 0; k < 8; ++k) q[k] = C.c[k * kWaveLanes];
   float4 val, du, dv, dw;
   tri_deriv4(q, L.u, L.v, L.w, val, du, dv, dw);
-  float W[8];
-  weights8(L.u, L.v, L.w, W);
   float Gb0, Gb1, Gb2;
   SphFrame F;
   if constexpr (KIND == RT_GRID_SPHERICAL_LOGR) {
@@ -148,18 +216,12 @@ __device__ __forceinline__ void eval_grad_adj(const DevGeom& g, const RayState& 
     Gb1 = gby * g.inv_sp[1];
     Gb2 = gbz * g.inv_sp[2];
   }
-#pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    float* a = A.v + k * kGradChannels * kWaveLanes;
-    a[0] = fmaf(W[k], nb, a[0]);
-    a[kWaveLanes] = fmaf(W[k], Gb0, a[kWaveLanes]);
-    a[2 * kWaveLanes] = fmaf(W[k], Gb1, a[2 * kWaveLanes]);
-    a[3 * kWaveLanes] = fmaf(W[k], Gb2, a[3 * kWaveLanes]);
-  }
+  log_entry(lg, e, L, WITH_N ? nb : 0.0f, Gb0, Gb1, Gb2, 0.0f);
   // adjoint of the continuous index (zero along an axis held at an edge)
-  const float xb0 = L.cl0 ? 0.0f : nb * du.x + Gb0 * du.y + Gb1 * du.z + Gb2 * du.w;
-  const float xb1 = L.cl1 ? 0.0f : nb * dv.x + Gb0 * dv.y + Gb1 * dv.z + Gb2 * dv.w;
-  const float xb2 = L.cl2 ? 0.0f : nb * dw.x + Gb0 * dw.y + Gb1 * dw.z + Gb2 * dw.w;
+  const float nbe = WITH_N ? nb : 0.0f;
+  const float xb0 = L.cl0 ? 0.0f : nbe * du.x + Gb0 * du.y + Gb1 * du.z + Gb2 * du.w;
+  const float xb1 = L.cl1 ? 0.0f : nbe * dv.x + Gb0 * dv.y + Gb1 * dv.z + Gb2 * dv.w;
+  const float xb2 = L.cl2 ? 0.0f : nbe * dw.x + Gb0 * dw.y + Gb1 * dw.z + Gb2 * dw.w;
   if constexpr (KIND == RT_GRID_SPHERICAL_LOGR) {
     // sum_m xb_m grad xi_m
     const float a0 = xb0 * F.s0, a1 = xb1 * F.s1, a2 = xb2 * F.s2;
@@ -191,15 +253,15 @@ __device__ __forceinline__ void eval_grad_adj(const DevGeom& g, const RayState& 
   }
 }
 
-// Adjoint of eval_value at r_i + d: (n_b, T_b) -> position adjoint q, channel scatter.
+// Adjoint of eval_value at r_i + d: (n_b, T_b) -> position adjoint q; the
+// channel adjoints go to log entry e.
 template <int KIND>
-__device__ __forceinline__ void eval_value_adj(const DevGeom& g, const RayState& R, CellCache& C, GradAcc& A,
-                                               double* gacc, const StepOrigin& O, float dx, float dy, float dz,
-                                               float nb, float tb, float& qx, float& qy, float& qz) {
+__device__ __forceinline__ void eval_value_adj(const DevGeom& g, const RayState& R, CellCache& C, float* lg, int e,
+                                               const StepOrigin& O, float dx, float dy, float dz, float nb, float tb,
+                                               float& qx, float& qy, float& qz) {
   Loc L;
   locate<KIND>(g, O, dx, dy, dz, L);
   ensure_cell(g, R.nfg, R.te, C, L.key);
-  grad_select(g, A, gacc, L.key);
   float qn[8], qt[8];
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
@@ -209,14 +271,7 @@ __device__ __forceinline__ void eval_value_adj(const DevGeom& g, const RayState&
   float vn, dn0, dn1, dn2, vt, dt0, dt1, dt2;
   tri_deriv1(qn, L.u, L.v, L.w, vn, dn0, dn1, dn2);
   tri_deriv1(qt, L.u, L.v, L.w, vt, dt0, dt1, dt2);
-  float W[8];
-  weights8(L.u, L.v, L.w, W);
-#pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    float* a = A.v + k * kGradChannels * kWaveLanes;
-    a[0] = fmaf(W[k], nb, a[0]);
-    a[4 * kWaveLanes] = fmaf(W[k], tb, a[4 * kWaveLanes]);
-  }
+  log_entry(lg, e, L, nb, 0.0f, 0.0f, 0.0f, tb);
   const float xb0 = L.cl0 ? 0.0f : nb * dn0 + tb * dt0;
   const float xb1 = L.cl1 ? 0.0f : nb * dn1 + tb * dt1;
   const float xb2 = L.cl2 ? 0.0f : nb * dn2 + tb * dt2;
@@ -250,7 +305,7 @@ __device__ __forceinline__ float segment_dphi(float x) {
     return fmaf(s, x, -0.5f);
   }
   const float e = __builtin_amdgcn_exp2f(-1.44269504089f * x);
-  return (e * (1.0f + x) - 1.0f) / (x * x);
+  return (e * (1.0f + x) - 1.0f) * rcpf(x * x);
 }
 
 // Adjoint of the ray state carried backward along the ray.
@@ -261,14 +316,16 @@ struct AdjState {
 };
 
 // One step backward.  R holds the step's start state (r_i, p_i, its grid index,
-// the optical depth before the step, n = i); S holds the adjoint of the state
-// after the step and the brightness behind it, and is replaced by the adjoint of
-// the start state.  `code` is the termination code the forward step returned.
+// the optical depth before the step, n = i) and tp its forward record (field f
+// at tp[f * ts]): no model evaluation of the forward step is repeated, and the
+// step's derived quantities are recomputed from these with ray_step's
+// arithmetic.  S holds the adjoint of the state after the step and the
+// brightness behind it, and is replaced by the adjoint of the start state.  `code` is the termination code the forward step returned.
 // The tracing mode is a compile-time choice (kModeLos, kModeNoMag, kModeFull);
 // absorption is always on.
 template <int KIND, int MODE>
-__device__ void step_adjoint(const AdjointArgs& aa, const RayState& R, CellCache& C, GradAcc& A, int code, double wgt,
-                             AdjState& S) {
+__device__ __forceinline__ void step_adjoint(const AdjointArgs& aa, const RayState& R, const float* tp, size_t ts, CellCache& C,
+                             GradAcc& A, float* lg, int code, double wgt, AdjState& S) {
   static_assert(MODE == kModeLos || MODE == kModeNoMag || MODE == kModeFull, "fixed tracing mode");
   const TraceArgs& a = aa.t;
   const DevGeom& g = a.g;
@@ -276,7 +333,7 @@ __device__ void step_adjoint(const AdjointArgs& aa, const RayState& R, CellCache
   constexpr bool refr = MODE != kModeLos;
   constexpr bool mag = MODE == kModeFull;
 
-  // ---------------- forward recomputation (the arithmetic of ray_step) ----------------
+  // ---------------- forward values: the step's record plus the arithmetic of ray_step ----------------
   StepOrigin O;
   make_origin<KIND>(R, O);
   const float pxf = float(R.px), pyf = float(R.py), pzf = float(R.pz);
@@ -284,36 +341,22 @@ __device__ void step_adjoint(const AdjointArgs& aa, const RayState& R, CellCache
   double hd;
   double drx, dry, drz;
   float d2x = 0.f, d2y = 0.f, d2z = 0.f, d3x = 0.f, d3y = 0.f, d3z = 0.f;
-  float F1x = 0.f, F1y = 0.f, F1z = 0.f, F2x = 0.f, F2y = 0.f, F2z = 0.f, F3x = 0.f, F3y = 0.f, F3z = 0.f;
-  float sx = 0.f, sy = 0.f, sz = 0.f, tx = 0.f, ty = 0.f, tz = 0.f;
+  float F1x = 0.f, F1y = 0.f, F1z = 0.f, F2x = 0.f, F2y = 0.f, F2z = 0.f;
+  float sx = 0.f, sy = 0.f, sz = 0.f;
   float ni = 0.f;
   bool floored = true;
   if constexpr (refr) {
-    float ne, gx, gy, gz;
-    eval_grad<KIND>(g, R.nfg, R.te, C, O, 0.f, 0.f, 0.f, ne, gx, gy, gz);
-    F1x = R.cf * gx; F1y = R.cf * gy; F1z = R.cf * gz;
-    sx = gx; sy = gy; sz = gz;
-    tx = gx; ty = gy; tz = gz;
-    const float n2 = 1.0f - R.xff * ne;
-    ni = n2 > 0.f ? sqrtf(n2) : 0.f;
+    ni = tp[kTapeNi * ts];
     floored = !(ni > a.n_floor);
-    hd = floored ? a.ds_max_d / a.n_floor_d : a.ds_max_d * rcp64(double(ni));
+    hd = floored ? a.ds_max_d * rcp64(a.n_floor_d) : a.ds_max_d * rcp64(double(ni));
     h = float(hd);
     hh = 0.5f * h;
     hq = hh * hh;
+    F1x = tp[kTapeF1 * ts]; F1y = tp[(kTapeF1 + 1) * ts]; F1z = tp[(kTapeF1 + 2) * ts];
+    F2x = tp[kTapeF2 * ts]; F2y = tp[(kTapeF2 + 1) * ts]; F2z = tp[(kTapeF2 + 2) * ts];
+    sx = tp[kTapeS * ts]; sy = tp[(kTapeS + 1) * ts]; sz = tp[(kTapeS + 2) * ts];
     d2x = hh * pxf; d2y = hh * pyf; d2z = hh * pzf;
-    eval_grad<KIND>(g, R.nfg, R.te, C, O, d2x, d2y, d2z, ne, gx, gy, gz);
-    F2x = R.cf * gx; F2y = R.cf * gy; F2z = R.cf * gz;
-    sx += gx; sy += gy; sz += gz;
-    tx = fmaf(2.f, gx, tx); ty = fmaf(2.f, gy, ty); tz = fmaf(2.f, gz, tz);
     d3x = hh * (pxf + hh * F1x); d3y = hh * (pyf + hh * F1y); d3z = hh * (pzf + hh * F1z);
-    eval_grad<KIND>(g, R.nfg, R.te, C, O, d3x, d3y, d3z, ne, gx, gy, gz);
-    F3x = R.cf * gx; F3y = R.cf * gy; F3z = R.cf * gz;
-    sx += gx; sy += gy; sz += gz;
-    tx = fmaf(2.f, gx, tx); ty = fmaf(2.f, gy, ty); tz = fmaf(2.f, gz, tz);
-    eval_grad<KIND>(g, R.nfg, R.te, C, O, h * (pxf + hh * F2x), h * (pyf + hh * F2y), h * (pzf + hh * F2z), ne, gx,
-                    gy, gz);
-    tx += gx; ty += gy; tz += gz;
     const double c6 = R.cfd * hd * (1.0 / 6.0);
     drx = hd * R.px + hd * c6 * double(sx);
     dry = hd * R.py + hd * c6 * double(sy);
@@ -325,52 +368,34 @@ __device__ void step_adjoint(const AdjointArgs& aa, const RayState& R, CellCache
   }
 
   // chord, basis and the perturbed retraces
-  const double ds = sqrt(drx * drx + dry * dry + drz * drz);
+  const double ds2 = drx * drx + dry * dry + drz * drz;
+  const double inv_ds = rsqrt64(ds2);
+  const double ds = ds2 * inv_ds;
   double ux = 0, uy = 0, uz = 0;                  // chord direction t
   double e1x = 0, e1y = 0, e1z = 0, e2x = 0, e2y = 0, e2z = 0, ci = 0, eps = 0;
   double s1x = 0, s1y = 0, s1z = 0, s2x = 0, s2y = 0, s2z = 0, det = 1;
-  float qax = 0.f, qay = 0.f, qaz = 0.f, qbx = 0.f, qby = 0.f, qbz = 0.f;  // q1 = F(P1) - F1 of each perturbed ray
-  float aax = 0.f, aay = 0.f, aaz = 0.f, abx = 0.f, aby = 0.f, abz = 0.f;  // sum of force differences
   bool ybr = false;
   float lnM = 0.0f;
   const float hh6 = h * h * (1.0f / 6.0f);
   if constexpr (mag) {
-    const double inv_ds = 1.0 / ds;
     ux = drx * inv_ds; uy = dry * inv_ds; uz = drz * inv_ds;
     double c1x, c1y, c1z;
     ybr = fabs(uz) > 0.9;
     if (ybr) { c1x = uz; c1y = 0.0; c1z = -ux; }
     else { c1x = -uy; c1y = ux; c1z = 0.0; }
-    ci = 1.0 / sqrt(c1x * c1x + c1y * c1y + c1z * c1z);
+    ci = rsqrt64(c1x * c1x + c1y * c1y + c1z * c1z);
     e1x = c1x * ci; e1y = c1y * ci; e1z = c1z * ci;
     e2x = uy * e1z - uz * e1y; e2y = uz * e1x - ux * e1z; e2z = ux * e1y - uy * e1x;
     eps = double(a.eta) * ds;
-#pragma unroll 1
-    for (int jj = 0; jj < 2; ++jj) {
-      const double ex = jj ? e2x : e1x, ey = jj ? e2y : e1y, ez = jj ? e2z : e1z;
-      const double d0x = eps * ex, d0y = eps * ey, d0z = eps * ez;
-      const float fx = float(d0x), fy = float(d0y), fz = float(d0z);
-      float ne, gx, gy, gz;
-      eval_grad<KIND>(g, R.nfg, R.te, C, O, fx, fy, fz, ne, gx, gy, gz);
-      const float q1x = R.cf * gx - F1x, q1y = R.cf * gy - F1y, q1z = R.cf * gz - F1z;
-      eval_grad<KIND>(g, R.nfg, R.te, C, O, d2x + fx, d2y + fy, d2z + fz, ne, gx, gy, gz);
-      float ax = q1x + (R.cf * gx - F2x), ay = q1y + (R.cf * gy - F2y), az = q1z + (R.cf * gz - F2z);
-      eval_grad<KIND>(g, R.nfg, R.te, C, O, d3x + fx + hq * q1x, d3y + fy + hq * q1y, d3z + fz + hq * q1z, ne, gx,
-                      gy, gz);
-      ax += R.cf * gx - F3x; ay += R.cf * gy - F3y; az += R.cf * gz - F3z;
-      const double vx = d0x + double(hh6 * ax), vy = d0y + double(hh6 * ay), vz = d0z + double(hh6 * az);
-      if (jj == 0) {
-        s1x = vx; s1y = vy; s1z = vz;
-        qax = q1x; qay = q1y; qaz = q1z;
-        aax = ax; aay = ay; aaz = az;
-      } else {
-        s2x = vx; s2y = vy; s2z = vz;
-        qbx = q1x; qby = q1y; qbz = q1z;
-        abx = ax; aby = ay; abz = az;
-      }
-    }
+    // s_j = eps e_j + h^2/6 a_j, a_j the force-difference sums of the record
+    s1x = eps * e1x + double(hh6 * tp[kTapeA * ts]);
+    s1y = eps * e1y + double(hh6 * tp[(kTapeA + 1) * ts]);
+    s1z = eps * e1z + double(hh6 * tp[(kTapeA + 2) * ts]);
+    s2x = eps * e2x + double(hh6 * tp[(kTapeA + 3) * ts]);
+    s2y = eps * e2y + double(hh6 * tp[(kTapeA + 4) * ts]);
+    s2z = eps * e2z + double(hh6 * tp[(kTapeA + 5) * ts]);
     det = (s1y * s2z - s1z * s2y) * ux + (s1z * s2x - s1x * s2z) * uy + (s1x * s2y - s1y * s2x) * uz;
-    const double mm1 = fabs(det) / (eps * eps) - 1.0;
+    const double mm1 = fabs(det) * rcp64(eps * eps) - 1.0;
     lnM = fast_log1pf(float(mm1));
   }
 
@@ -380,15 +405,14 @@ __device__ void step_adjoint(const AdjointArgs& aa, const RayState& R, CellCache
   else if (code == kExit) lam = crossing<double>(R.rx, R.ry, R.rz, drx, dry, drz, g.r_max, true);
   const float hl = 0.5f * float(lam);
   const float mdx = hl * float(drx), mdy = hl * float(dry), mdz = hl * float(drz);
-  float ne_m, te_m;
-  eval_value<KIND>(g, R.nfg, R.te, C, O, mdx, mdy, mdz, ne_m, te_m);
+  const float ne_m = tp[kTapeNeM * ts], te_m = tp[kTapeTeM * ts];
   float kn, lnl, cl;
   double dtau;
   {
     const float lt = __builtin_amdgcn_logf(te_m) * 0.69314718056f;
     cl = (te_m >= 2.0e5f) ? 1.0f : 1.5f;
     lnl = (te_m >= 2.0e5f) ? 24.5f + lt - R.lnf : 18.2f + 1.5f * lt - R.lnf;
-    kn = kFFCoefF * ne_m * ne_m * lnl * rcpf(R.f2 * te_m * sqrtf(te_m));
+    kn = kFFCoefF * ne_m * ne_m * lnl * rcpf(R.f2 * te_m * sqrt_fast(te_m));
     dtau = double(kn) * (kRsunCm * lam * hd);
   }
   const double xs = dtau - lam * double(lnM);
@@ -416,14 +440,14 @@ __device__ void step_adjoint(const AdjointArgs& aa, const RayState& R, CellCache
     lam_b += dtau_b * double(kn) * kRsunCm * hd;
     hd_b += dtau_b * double(kn) * kRsunCm * lam;
     // kappa*n = C n_e^2 lnL / (f^2 T^1.5), lnL = c + cl ln T - ln f
-    ne_m_b = float(kn_b) * (2.0f * kFFCoefF * ne_m * lnl * rcpf(R.f2 * te_m * sqrtf(te_m)));
-    te_b += kn_b * double(kn) / double(te_m) * (double(cl) / double(lnl) - 1.5);
+    ne_m_b = float(kn_b) * (2.0f * kFFCoefF * ne_m * lnl * rcpf(R.f2 * te_m * sqrt_fast(te_m)));
+    te_b += kn_b * double(kn) * rcp64(double(te_m)) * (double(cl) * rcp64(double(lnl)) - 1.5);
   }
   double rbx = 0.0, rby = 0.0, rbz = 0.0;      // this step's contributions to d loss / d r_i
   double drbx = 0.0, drby = 0.0, drbz = 0.0;   // d loss / d (chord)
   {
     float qx, qy, qz;
-    eval_value_adj<KIND>(g, R, C, A, gacc, O, mdx, mdy, mdz, ne_m_b, float(te_b), qx, qy, qz);
+    eval_value_adj<KIND>(g, R, C, lg, 0, O, mdx, mdy, mdz, ne_m_b, float(te_b), qx, qy, qz);
     rbx += qx; rby += qy; rbz += qz;
     drbx += 0.5 * lam * qx; drby += 0.5 * lam * qy; drbz += 0.5 * lam * qz;
     lam_b += 0.5 * (double(qx) * drx + double(qy) * dry + double(qz) * drz);
@@ -433,7 +457,7 @@ __device__ void step_adjoint(const AdjointArgs& aa, const RayState& R, CellCache
     const double px = R.rx + lam * drx, py = R.ry + lam * dry, pz = R.rz + lam * drz;
     const double den = px * drx + py * dry + pz * drz;
     if (den != 0.0) {
-      const double c = -lam_b / den;
+      const double c = -lam_b * rcp64(den);
       rbx += c * px; rby += c * py; rbz += c * pz;
       drbx += c * lam * px; drby += c * lam * py; drbz += c * lam * pz;
     }
@@ -445,8 +469,8 @@ __device__ void step_adjoint(const AdjointArgs& aa, const RayState& R, CellCache
   double hq_b = 0.0;
   if constexpr (mag) {
     // ln M = ln|det| - 2 ln eps, det = (s1 x s2) . t
-    const double det_b = lnM_b / det;
-    double eps_b = -2.0 * lnM_b / eps;
+    const double det_b = lnM_b * rcp64(det);
+    double eps_b = -2.0 * lnM_b * rcp64(eps);
     const double sb1x = det_b * (s2y * uz - s2z * uy), sb1y = det_b * (s2z * ux - s2x * uz),
                  sb1z = det_b * (s2x * uy - s2y * ux);
     const double sb2x = det_b * (uy * s1z - uz * s1y), sb2y = det_b * (uz * s1x - ux * s1z),
@@ -458,8 +482,10 @@ __device__ void step_adjoint(const AdjointArgs& aa, const RayState& R, CellCache
     for (int jj = 0; jj < 2; ++jj) {
       const double ex_ = jj ? e2x : e1x, ey_ = jj ? e2y : e1y, ez_ = jj ? e2z : e1z;
       const double sbx = jj ? sb2x : sb1x, sby = jj ? sb2y : sb1y, sbz = jj ? sb2z : sb1z;
-      const float ajx = jj ? abx : aax, ajy = jj ? aby : aay, ajz = jj ? abz : aaz;
-      const float qjx = jj ? qbx : qax, qjy = jj ? qby : qay, qjz = jj ? qbz : qaz;
+      const float* aj = tp + size_t(kTapeA + 3 * jj) * ts;
+      const float* qj = tp + size_t(kTapeQ + 3 * jj) * ts;
+      const float ajx = aj[0], ajy = aj[ts], ajz = aj[2 * ts];
+      const float qjx = qj[0], qjy = qj[ts], qjz = qj[2 * ts];
       const float fx = float(eps * ex_), fy = float(eps * ey_), fz = float(eps * ez_);
       // s_j = eps e_j + h^2/6 a_j
       eps_b += sbx * ex_ + sby * ey_ + sbz * ez_;
@@ -468,7 +494,7 @@ __device__ void step_adjoint(const AdjointArgs& aa, const RayState& R, CellCache
       hd_b += (double(h) / 3.0) * (double(ajx) * sbx + double(ajy) * sby + double(ajz) * sbz);
       // third stage of the perturbed ray at d3 + d0 + hq q1
       float p3x, p3y, p3z;
-      eval_grad_adj<KIND>(g, R, C, A, gacc, O, d3x + fx + hq * qjx, d3y + fy + hq * qjy, d3z + fz + hq * qjz,
+      eval_grad_adj<KIND>(g, R, C, lg, 1 + 3 * jj, O, d3x + fx + hq * qjx, d3y + fy + hq * qjy, d3z + fz + hq * qjz,
                           R.cf * abx_, R.cf * aby_, R.cf * abz_, 0.0f, p3x, p3y, p3z);
       rbx += p3x; rby += p3y; rbz += p3z;
       d3bx += p3x; d3by += p3y; d3bz += p3z;
@@ -478,7 +504,7 @@ __device__ void step_adjoint(const AdjointArgs& aa, const RayState& R, CellCache
       g3bx -= R.cf * abx_; g3by -= R.cf * aby_; g3bz -= R.cf * abz_;
       // second stage at d2 + d0
       float p2x, p2y, p2z;
-      eval_grad_adj<KIND>(g, R, C, A, gacc, O, d2x + fx, d2y + fy, d2z + fz, R.cf * abx_, R.cf * aby_,
+      eval_grad_adj<KIND>(g, R, C, lg, 2 + 3 * jj, O, d2x + fx, d2y + fy, d2z + fz, R.cf * abx_, R.cf * aby_,
                           R.cf * abz_, 0.0f, p2x, p2y, p2z);
       rbx += p2x; rby += p2y; rbz += p2z;
       d2bx += p2x; d2by += p2y; d2bz += p2z;
@@ -486,7 +512,8 @@ __device__ void step_adjoint(const AdjointArgs& aa, const RayState& R, CellCache
       g2bx -= R.cf * abx_; g2by -= R.cf * aby_; g2bz -= R.cf * abz_;
       // first stage at d0: q1 = cf G(P1) - F1
       float p1x, p1y, p1z;
-      eval_grad_adj<KIND>(g, R, C, A, gacc, O, fx, fy, fz, R.cf * qtx, R.cf * qty, R.cf * qtz, 0.0f, p1x, p1y, p1z);
+      eval_grad_adj<KIND>(g, R, C, lg, 3 + 3 * jj, O, fx, fy, fz, R.cf * qtx, R.cf * qty, R.cf * qtz, 0.0f, p1x, p1y,
+                          p1z);
       rbx += p1x; rby += p1y; rbz += p1z;
       d0bx += p1x; d0by += p1y; d0bz += p1z;
       g1bx -= R.cf * qtx; g1by -= R.cf * qty; g1bz -= R.cf * qtz;
@@ -496,6 +523,7 @@ __device__ void step_adjoint(const AdjointArgs& aa, const RayState& R, CellCache
       if (jj == 0) { e1bx += ebx; e1by += eby; e1bz += ebz; }
       else { e2bx += ebx; e2by += eby; e2bz += ebz; }
     }
+    log_replay(g, A, gacc, lg, 7);
     // e2 = t x e1
     tbx += e1y * e2bz - e1z * e2by; tby += e1z * e2bx - e1x * e2bz; tbz += e1x * e2by - e1y * e2bx;
     e1bx += e2by * uz - e2bz * uy; e1by += e2bz * ux - e2bx * uz; e1bz += e2bx * uy - e2by * ux;
@@ -507,7 +535,6 @@ __device__ void step_adjoint(const AdjointArgs& aa, const RayState& R, CellCache
     // eps = eta ds; t = dr / ds; ds = |dr|
     const double ds_b = double(a.eta) * eps_b;
     const double tt = ux * tbx + uy * tby + uz * tbz;
-    const double inv_ds = 1.0 / ds;
     drbx += (tbx - ux * tt) * inv_ds + ds_b * ux;
     drby += (tby - uy * tt) * inv_ds + ds_b * uy;
     drbz += (tbz - uz * tt) * inv_ds + ds_b * uz;
@@ -518,6 +545,9 @@ __device__ void step_adjoint(const AdjointArgs& aa, const RayState& R, CellCache
   rbx += S.rbx; rby += S.rby; rbz += S.rbz;
   double pbx = S.pbx, pby = S.pby, pbz = S.pbz;
   if constexpr (refr) {
+    // log entries of the central stages: after the midpoint value (entry 0) unless
+    // the perturbed retraces' replay has already taken it
+    const int e0 = mag ? 0 : 1;
     const double dpbx = S.pbx, dpby = S.pby, dpbz = S.pbz;
     // dr = h p + (h^2 / 6) cf s, dp = (h / 6) cf t
     hd_b += drbx * R.px + drby * R.py + drbz * R.pz +
@@ -525,7 +555,8 @@ __device__ void step_adjoint(const AdjointArgs& aa, const RayState& R, CellCache
     pbx += hd * drbx; pby += hd * drby; pbz += hd * drbz;
     const double ks = hd * hd * (1.0 / 6.0) * R.cfd;
     const float sbx = float(ks * drbx), sby = float(ks * drby), sbz = float(ks * drbz);
-    hd_b += (R.cfd / 6.0) * (dpbx * double(tx) + dpby * double(ty) + dpbz * double(tz));
+    hd_b += (R.cfd / 6.0) * (dpbx * double(tp[kTapeT * ts]) + dpby * double(tp[(kTapeT + 1) * ts]) +
+                             dpbz * double(tp[(kTapeT + 2) * ts]));
     const double kt = hd * (1.0 / 6.0) * R.cfd;
     const float tbx_ = float(kt * dpbx), tby_ = float(kt * dpby), tbz_ = float(kt * dpbz);
     g1bx += sbx + tbx_; g1by += sby + tby_; g1bz += sbz + tbz_;
@@ -533,7 +564,7 @@ __device__ void step_adjoint(const AdjointArgs& aa, const RayState& R, CellCache
     g3bx += sbx + 2.f * tbx_; g3by += sby + 2.f * tby_; g3bz += sbz + 2.f * tbz_;
     float qx, qy, qz;
     // fourth stage at d4 = h (p + hh F2) = h p + (h^2 / 2) cf g2
-    eval_grad_adj<KIND>(g, R, C, A, gacc, O, h * (pxf + hh * F2x), h * (pyf + hh * F2y), h * (pzf + hh * F2z), tbx_,
+    eval_grad_adj<KIND>(g, R, C, lg, e0, O, h * (pxf + hh * F2x), h * (pyf + hh * F2y), h * (pzf + hh * F2z), tbx_,
                         tby_, tbz_, 0.0f, qx, qy, qz);
     rbx += qx; rby += qy; rbz += qz;
     hd_b += double(qx) * (R.px + hd * double(F2x)) + double(qy) * (R.py + hd * double(F2y)) +
@@ -542,7 +573,7 @@ __device__ void step_adjoint(const AdjointArgs& aa, const RayState& R, CellCache
     const float k4 = 0.5f * h * h * R.cf;
     g2bx += k4 * qx; g2by += k4 * qy; g2bz += k4 * qz;
     // third stage at d3 = hh p + hq cf g1
-    eval_grad_adj<KIND>(g, R, C, A, gacc, O, d3x, d3y, d3z, g3bx, g3by, g3bz, 0.0f, qx, qy, qz);
+    eval_grad_adj<KIND>(g, R, C, lg, e0 + 1, O, d3x, d3y, d3z, g3bx, g3by, g3bz, 0.0f, qx, qy, qz);
     rbx += qx; rby += qy; rbz += qz;
     d3bx += qx; d3by += qy; d3bz += qz;
     hd_b += double(d3bx) * (0.5 * R.px + 0.5 * hd * double(F1x)) + double(d3by) * (0.5 * R.py + 0.5 * hd * double(F1y)) +
@@ -551,7 +582,7 @@ __device__ void step_adjoint(const AdjointArgs& aa, const RayState& R, CellCache
     const float k3 = hq * R.cf;
     g1bx += k3 * d3bx; g1by += k3 * d3by; g1bz += k3 * d3bz;
     // second stage at d2 = hh p
-    eval_grad_adj<KIND>(g, R, C, A, gacc, O, d2x, d2y, d2z, g2bx, g2by, g2bz, 0.0f, qx, qy, qz);
+    eval_grad_adj<KIND>(g, R, C, lg, e0 + 2, O, d2x, d2y, d2z, g2bx, g2by, g2bz, 0.0f, qx, qy, qz);
     rbx += qx; rby += qy; rbz += qz;
     d2bx += qx; d2by += qy; d2bz += qz;
     hd_b += 0.5 * (double(d2bx) * R.px + double(d2by) * R.py + double(d2bz) * R.pz);
@@ -561,14 +592,17 @@ __device__ void step_adjoint(const AdjointArgs& aa, const RayState& R, CellCache
     // dt = ds_max / n(r_i), n = sqrt(1 - Xf n_e)
     float ne1_b = 0.0f;
     if (!floored) {
-      const double n_b = -(hd / double(ni)) * hd_b;
-      ne1_b = float(-(double(R.xff) / (2.0 * double(ni))) * n_b);
+      const double rni = rcp64(double(ni));
+      const double n_b = -(hd * rni) * hd_b;
+      ne1_b = float(-(0.5 * double(R.xff) * rni) * n_b);
     }
     // first stage at r_i (gradient and the value that set the step)
-    eval_grad_adj<KIND>(g, R, C, A, gacc, O, 0.f, 0.f, 0.f, g1bx, g1by, g1bz, ne1_b, qx, qy, qz);
+    eval_grad_adj<KIND, true>(g, R, C, lg, e0 + 3, O, 0.f, 0.f, 0.f, g1bx, g1by, g1bz, ne1_b, qx, qy, qz);
     rbx += qx; rby += qy; rbz += qz;
+    log_replay(g, A, gacc, lg, e0 + 4);
   } else {
     pbx += hd * drbx; pby += hd * drby; pbz += hd * drbz;
+    log_replay(g, A, gacc, lg, 1);
   }
   S.rbx = rbx; S.rby = rby; S.rbz = rbz;
   S.pbx = pbx; S.pby = pby; S.pbz = pbz;
@@ -601,6 +635,11 @@ __device__ __forceinline__ void state_load(const double* buf, int entry, int lim
   R.code = kRunning;
 }
 
+// Record of chunk step `entry` (0 <= entry < K, which the chunk loop keeps).
+__device__ __forceinline__ float* tape_entry(const AdjointArgs& aa, int entry, int slot) {
+  return aa.tape + size_t(entry) * kTapeFields * size_t(aa.n_slots) + slot;
+}
+
 __device__ __forceinline__ void state_copy(double* buf, int from, int to, int limit, int n_slots, int slot) {
   if ((unsigned)from >= (unsigned)limit || (unsigned)to >= (unsigned)limit) return;
   const size_t s = size_t(n_slots);
@@ -612,10 +651,11 @@ __device__ __forceinline__ void state_copy(double* buf, int from, int to, int li
 // One ray: the forward trace with checkpoints every kr steps (kr starts at K
 // and doubles, with every other checkpoint dropped, whenever the ray outgrows
 // the checkpoint capacity), then the reverse sweep segment by segment: each
-// chunk of at most K steps is recomputed from its checkpoint into the step
-// buffer and swept backward.  Adds w T_b to `loss` and writes T_b.
+// chunk of at most K steps is recomputed from its checkpoint, writing each
+// step's start state and forward record, and swept backward.  Adds w T_b to
+// `loss` and writes T_b.
 template <int KIND, int MODE>
-__device__ void adjoint_ray(const AdjointArgs& aa, int img, int pix, int slot, CellCache& C, GradAcc& A,
+__device__ __forceinline__ void adjoint_ray(const AdjointArgs& aa, int img, int pix, int slot, CellCache& C, GradAcc& A, float* lg,
                             double& loss) {
   const TraceArgs& a = aa.t;
   const int npx = a.nu * a.nv;
@@ -627,6 +667,7 @@ __device__ void adjoint_ray(const AdjointArgs& aa, int img, int pix, int slot, C
     return;
   }
   const int K = aa.K;
+  const size_t ts = size_t(aa.n_slots);
   int kr = K, nc = 0, code;
   do {
     if (R.n % kr == 0) {
@@ -638,7 +679,7 @@ __device__ void adjoint_ray(const AdjointArgs& aa, int img, int pix, int slot, C
       state_store(aa.ckpt, nc, aa.ckpt_cap, aa.n_slots, slot, R);
       ++nc;
     }
-    code = ray_step<true, KIND, MODE>(a, R, C);
+    code = ray_step<true, KIND, MODE, true>(a, R, C, nullptr, ts);
   } while (code == kRunning);
   finish_ray(a, R);
   const int N = R.n;
@@ -657,15 +698,20 @@ __device__ void adjoint_ray(const AdjointArgs& aa, int img, int pix, int slot, C
       const int c0 = max(s0, c1 - K);
       state_load(aa.ckpt, seg, aa.ckpt_cap, aa.n_slots, slot, R);
       R.n = s0;
-      while (R.n < c0) ray_step<true, KIND, MODE>(a, R, C);
-      for (int i = c0; i < c1; ++i) {
-        state_store(aa.steps, i - c0, aa.K, aa.n_slots, slot, R);
-        if (i + 1 < c1) ray_step<true, KIND, MODE>(a, R, C);
+      // steps s0 .. c0-1 are only retraced; steps c0 .. c1-1 are recorded
+      while (R.n < c1) {
+        float* tp = nullptr;
+        if (R.n >= c0) {
+          state_store(aa.steps, R.n - c0, aa.K, aa.n_slots, slot, R);
+          tp = tape_entry(aa, R.n - c0, slot);
+        }
+        ray_step<true, KIND, MODE, true>(a, R, C, tp, ts);
       }
       for (int i = c1 - 1; i >= c0; --i) {
         state_load(aa.steps, i - c0, aa.K, aa.n_slots, slot, R);
         R.n = i;
-        step_adjoint<KIND, MODE>(aa, R, C, A, (i == N - 1) ? code : kRunning, wgt, S);
+        step_adjoint<KIND, MODE>(aa, R, tape_entry(aa, i - c0, slot), ts, C, A, lg, (i == N - 1) ? code : kRunning,
+                                 wgt, S);
       }
     }
   }
@@ -674,13 +720,14 @@ __device__ void adjoint_ray(const AdjointArgs& aa, int img, int pix, int slot, C
     const float ne0 = a.launch_ne[pix];
     const float n2 = 1.0f - R.xff * ne0;
     if (n2 > 0.f) {
-      const float nidx = sqrtf(n2);
+      const float nidx = sqrt_fast(n2);
       const double n_b = -(a.o[0] * S.pbx + a.o[1] * S.pby + a.o[2] * S.pbz);
-      const float ne_b = float(-(double(R.xff) / (2.0 * double(nidx))) * n_b);
+      const float ne_b = float(-(0.5 * double(R.xff) * rcp64(double(nidx))) * n_b);
       StepOrigin O;
       make_origin<KIND>(R, O);
       float qx, qy, qz;
-      eval_value_adj<KIND>(a.g, R, C, A, aa.gacc, O, 0.f, 0.f, 0.f, ne_b, 0.0f, qx, qy, qz);
+      eval_value_adj<KIND>(a.g, R, C, lg, 0, O, 0.f, 0.f, 0.f, ne_b, 0.0f, qx, qy, qz);
+      log_replay(a.g, A, aa.gacc, lg, 1);
     }
   }
 }

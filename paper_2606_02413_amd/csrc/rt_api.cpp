@@ -570,10 +570,11 @@ rt_status rt_trace_adjoint(const rt_model* model, const double* freq_hz, int32_t
     const long long n_slots = blocks * 256;
     const size_t ck_bytes = size_t(cap) * kCkptFields * size_t(n_slots) * sizeof(double);
     const size_t st_bytes = size_t(K) * kCkptFields * size_t(n_slots) * sizeof(double);
+    const size_t tp_bytes = size_t(K) * kTapeFields * size_t(n_slots) * sizeof(float);
     const long long nvp = (long long)a.g.n0 * a.g.n1 * a.g.n2p;
     const size_t acc_bytes = size_t(nvp) * kGradChannels * sizeof(double);
     const size_t tb_bytes = tb_out ? 0 : size_t(npx) * size_t(n_freq) * sizeof(float);
-    const size_t need = ck_bytes + st_bytes + acc_bytes + tb_bytes + 256 * 4;
+    const size_t need = ck_bytes + st_bytes + tp_bytes + acc_bytes + tb_bytes + 256 * 4;
     char* ws = nullptr;
     {
       std::lock_guard<std::mutex> lk(g_scratch_mu);
@@ -592,6 +593,7 @@ rt_status rt_trace_adjoint(const rt_model* model, const double* freq_hz, int32_t
     aa.gacc = reinterpret_cast<double*>(ws + off); off += acc_bytes;
     aa.ckpt = reinterpret_cast<double*>(ws + off); off += ck_bytes;
     aa.steps = reinterpret_cast<double*>(ws + off); off += st_bytes;
+    aa.tape = reinterpret_cast<float*>(ws + off); off += tp_bytes;
     float* tb = tb_out ? tb_out : reinterpret_cast<float*>(ws + off);
     a.tb = tb;
     a.info = nullptr;

@@ -68,13 +68,21 @@ struct TraceArgs {
 // with checkpoints, then its reverse sweep.
 constexpr int kCkptFields = 10;   // r (3), p (3), grid index (3), optical depth so far
 constexpr int kGradChannels = 5;  // per vertex: n_e, the three index-space gradient channels, T
+// Per-step record of the forward quantities the reverse sweep needs (FP32):
+// n(r_i), F1, F2, sum g1+g2+g3, g1+2g2+2g3+g4, q1 and the force-difference sums
+// of the two perturbed retraces, n_e and T at the chord midpoint.
+enum : int {
+  kTapeNi = 0, kTapeF1 = 1, kTapeF2 = 4, kTapeS = 7, kTapeT = 10, kTapeQ = 13, kTapeA = 19,
+  kTapeNeM = 25, kTapeTeM = 26, kTapeFields = 27
+};
 struct AdjointArgs {
   TraceArgs t;                // one model, image layout [freq][nv][nu]
   const float* weights;       // [n_freq][nv][nu]
   double* loss;               // device scalar, accumulated
   double* gacc;               // [n0 * n1 * n2p][kGradChannels] channel adjoints, zeroed before launch
   double* ckpt;               // [ckpt_cap][kCkptFields][n_slots]
-  double* steps;              // [K][kCkptFields][n_slots]
+  double* steps;              // [K][kCkptFields][n_slots] start state of each step of a chunk
+  float* tape;                // [K][kTapeFields][n_slots] forward record of each step of a chunk
   unsigned* counter;          // tile claim counter, zeroed before launch
   int K, ckpt_cap, n_slots, n_tiles;
 };

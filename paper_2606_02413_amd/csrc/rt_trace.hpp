@@ -64,6 +64,15 @@ __device__ __forceinline__ float fast_atan2f(float y, float x) {
   return copysignf(r, y);
 }
 
+// Angle of a small increment: atan2(y, x) for x > 0 and |y| <= tan(pi/8) x takes
+// the series after one reciprocal (no octant reduction); any other argument
+// goes through fast_atan2f.  The angular increments from a step's origin to its
+// evaluation points are this small except next to the polar axis.
+__device__ __forceinline__ float atan2_inc(float y, float x) {
+  if (x > 0.0f && fabsf(y) <= 0.41421356f * x) return atan_poly(y * rcpf(x));
+  return fast_atan2f(y, x);
+}
+
 // log1p in FP32: 2 atanh(z / (2 + z)) by its odd series for |z| <= 1/4
 // (relative truncation below 1e-10); log2 instruction otherwise.
 __device__ __forceinline__ float fast_log1pf(float z) {
@@ -87,6 +96,26 @@ __device__ __forceinline__ double rcp64(double x) {
   y = fma(y, fma(-x, y, 1.0), y);
   return y;
 }
+
+// Square roots without the correctly rounded expansion the compiler emits for
+// sqrt(): FP32 with the hardware instruction (about 1 ulp), FP64 as x rsqrt(x)
+// with the hardware estimate refined by two Newton steps (full FP64 accuracy,
+// not correctly rounded).  0 for x <= 0.
+__device__ __forceinline__ float sqrt_fast(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ double rsqrt64(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  const double hx = 0.5 * x;
+  y = y * fma(-hx * y, y, 1.5);
+  y = y * fma(-hx * y, y, 1.5);
+  return y;
+}
+__device__ __forceinline__ double sqrt64(double x) { return x > 0.0 ? x * rsqrt64(x) : 0.0; }
+// The same for the precision of the ray-tube area (double, or float in the
+// all-FP32 variant).
+__device__ __forceinline__ double rsqrt_r(double x) { return rsqrt64(x); }
+__device__ __forceinline__ float rsqrt_r(float x) { return rsqrtf(x); }
+__device__ __forceinline__ double rcp_r(double x) { return rcp64(x); }
+__device__ __forceinline__ float rcp_r(float x) { return rcpf(x); }
 
 // FP64 series for the per-step index increments, valid for small arguments
 // only (|w|, |t| <= 1/32): three shared coefficients keep the loop free of
@@ -253,14 +282,14 @@ __device__ __forceinline__ void locate(const DevGeom& g, const StepOrigin& O, fl
     const float c = 2.0f * (rd + O.z * dz) + (dd + dz * dz);
     x0 = O.f0 + 0.5f * fast_log1pf(c * O.inv_r2) * g.inv_dl;
     // azimuth: angle from (x_i, y_i) to (x_i + dx, y_i + dy)
-    x2 = O.f2 + fast_atan2f(O.x * dy - O.y * dx, O.rho2 + rd) * g.inv_dph;
+    x2 = O.f2 + atan2_inc(O.x * dy - O.y * dx, O.rho2 + rd) * g.inv_dph;
     // colatitude: angle from (z_i, rho_i) to (z_q, rho_q) in the meridional plane
     const float e = 2.0f * rd + dd;
-    const float rhoq = sqrtf(fmaxf(O.rho2 + e, 0.0f));
+    const float rhoq = sqrt_fast(fmaxf(O.rho2 + e, 0.0f));
     const float den = rhoq + O.rho;
     const float drho = den > 0.0f ? e * rcpf(den) : 0.0f;
     const float zq = O.z + dz;
-    x1 = O.f1 + fast_atan2f(O.z * drho - O.rho * dz, O.z * zq + O.rho * rhoq) * g.inv_dth;
+    x1 = O.f1 + atan2_inc(O.z * drho - O.rho * dz, O.z * zq + O.rho * rhoq) * g.inv_dth;
     L.rinv = rsqrtf(O.r2 + c);
     L.rho = rhoq;
     L.axis = rhoq < 1e-12f;
@@ -427,7 +456,7 @@ __device__ __forceinline__ void make_origin(const RayState& R, StepOrigin& O) {
   double rho;
   O.x = float(R.rx); O.y = float(R.ry); O.z = float(R.rz);
   if constexpr (KIND == RT_GRID_SPHERICAL_LOGR) {
-    rho = sqrt(rho2);
+    rho = sqrt64(rho2);
     O.r2 = float(r2); O.inv_r2 = float(rcp64(r2)); O.rho2 = float(rho2); O.rho = float(rho);
   } else {
     rho = 0.0;
@@ -444,7 +473,7 @@ template <int KIND>
 __device__ __forceinline__ void index_advance(const DevGeom& g, RayState& R, double dx, double dy, double dz) {
   if constexpr (KIND == RT_GRID_SPHERICAL_LOGR) {
     const double X = R.rx, Y = R.ry, Z = R.rz;  // old origin
-    const double rho2 = X * X + Y * Y, r2 = rho2 + Z * Z, rho = sqrt(rho2);
+    const double rho2 = X * X + Y * Y, r2 = rho2 + Z * Z, rho = sqrt64(rho2);
     const double rd = X * dx + Y * dy;
     const double dd = dx * dx + dy * dy;
     const double c = 2.0 * (rd + Z * dz) + (dd + dz * dz);
@@ -465,7 +494,7 @@ __device__ __forceinline__ void index_advance(const DevGeom& g, RayState& R, dou
     if (R.b2 >= double(g.n2)) R.b2 -= double(g.n2);
     // colatitude
     const double e = 2.0 * rd + dd;
-    const double rhoq = sqrt(fmax(rho2 + e, 0.0));
+    const double rhoq = sqrt64(rho2 + e);
     const double dsum = rhoq + rho;
     const double drho = dsum > 0.0 ? e * rcp64(dsum) : 0.0;
     const double numt = Z * drho - rho * dz, dent = Z * nZ + rho * rhoq;
@@ -517,7 +546,7 @@ __device__ __forceinline__ bool init_ray(const TraceArgs& a, int img, int pix, R
   double nidx = 1.0;
   if (a.flags & RT_USE_REFRACTION) {
     const float n2 = 1.0f - R.xff * a.launch_ne[size_t(model) * npx + pix];
-    nidx = n2 > 0.f ? double(sqrtf(n2)) : 0.0;
+    nidx = n2 > 0.f ? double(sqrt_fast(n2)) : 0.0;
   }
   R.px = -nidx * a.o[0]; R.py = -nidx * a.o[1]; R.pz = -nidx * a.o[2];
   R.A = 0.0; R.lam_tot = 0.0; R.tau = 0.0; R.lns = 0.0; R.s_arc = 0.0;
@@ -544,7 +573,7 @@ __device__ __forceinline__ void finish_ray(const TraceArgs& a, const RayState& R
     inf.exit_pos[0] = float(R.rx); inf.exit_pos[1] = float(R.ry); inf.exit_pos[2] = float(R.rz);
     inf.tau = float(R.tau);
     inf.ln_s_end = float(R.lns);
-    inf.r_min = fminf(R.rmin, float(sqrt(R.rx * R.rx + R.ry * R.ry + R.rz * R.rz)));
+    inf.r_min = fminf(R.rmin, sqrt_fast(float(R.rx * R.rx + R.ry * R.ry + R.rz * R.rz)));
     a.info[R.id] = inf;
   }
   if (R.path_slot >= 0) a.path_len[R.path_slot] = R.path_len;
@@ -561,7 +590,7 @@ __device__ __forceinline__ float segment_phi(float x) {
     s = fmaf(s, -x, 0.5f);
     return fmaf(s, -x, 1.0f);
   }
-  return (1.0f - __builtin_amdgcn_exp2f(-1.44269504089f * x)) / x;
+  return (1.0f - __builtin_amdgcn_exp2f(-1.44269504089f * x)) * rcpf(x);
 }
 
 // Tracing mode of ray_step: from the call's flags, or fixed at compile time.
@@ -570,8 +599,11 @@ enum : int { kModeFlags = 0, kModeLos = 1, kModeNoMag = 2, kModeFull = 3 };
 // One central RK4 step with its two perturbed retraces, termination test and
 // transfer segment.  Returns the termination code (kRunning to continue); on
 // termination R holds the end point, the code and the last-step fraction.
-template <bool MIXED, int KIND, int MODE = kModeFlags>
-__device__ int ray_step(const TraceArgs& a, RayState& R, CellCache& C) {
+// TAPE: when tp is not null, also write the step's record (fields kTape*,
+// field f at tp[f * ts]).
+template <bool MIXED, int KIND, int MODE = kModeFlags, bool TAPE = false>
+__device__ __forceinline__ int ray_step(const TraceArgs& a, RayState& R, CellCache& C, float* tp = nullptr,
+                                         size_t ts = 0) {
   using Real = typename RealOf<MIXED>::T;
   const bool refr = (MODE == kModeFlags) ? (a.flags & RT_USE_REFRACTION) != 0 : (MODE != kModeLos);
   const bool mag = (MODE == kModeFlags) ? refr && (a.flags & RT_USE_MAGNIFICATION) != 0 : (MODE == kModeFull);
@@ -593,13 +625,18 @@ __device__ int ray_step(const TraceArgs& a, RayState& R, CellCache& C) {
     float sx = gx, sy = gy, sz = gz;                  // g1 + g2 + g3
     float tx = gx, ty = gy, tz = gz;                  // g1 + 2 g2 + 2 g3 + g4
     const float n2 = 1.0f - R.xff * ne;
-    const float ni = n2 > 0.f ? sqrtf(n2) : 0.f;
-    hd = (ni > a.n_floor) ? a.ds_max_d * rcp64(double(ni)) : a.ds_max_d / a.n_floor_d;
+    const float ni = n2 > 0.f ? sqrt_fast(n2) : 0.f;
+    if (TAPE && tp) {
+      tp[kTapeNi * ts] = ni;
+      tp[kTapeF1 * ts] = F1x; tp[(kTapeF1 + 1) * ts] = F1y; tp[(kTapeF1 + 2) * ts] = F1z;
+    }
+    hd = (ni > a.n_floor) ? a.ds_max_d * rcp64(double(ni)) : a.ds_max_d * rcp64(a.n_floor_d);
     h = float(hd);
     const float hh = 0.5f * h;
     d2x = hh * pxf; d2y = hh * pyf; d2z = hh * pzf;
     eval_grad<KIND>(a.g, R.nfg, R.te, C, O, d2x, d2y, d2z, ne, gx, gy, gz);
     F2x = R.cf * gx; F2y = R.cf * gy; F2z = R.cf * gz;
+    if (TAPE && tp) { tp[kTapeF2 * ts] = F2x; tp[(kTapeF2 + 1) * ts] = F2y; tp[(kTapeF2 + 2) * ts] = F2z; }
     sx += gx; sy += gy; sz += gz;
     tx = fmaf(2.f, gx, tx); ty = fmaf(2.f, gy, ty); tz = fmaf(2.f, gz, tz);
     d3x = hh * (pxf + hh * F1x); d3y = hh * (pyf + hh * F1y); d3z = hh * (pzf + hh * F1z);
@@ -610,6 +647,10 @@ __device__ int ray_step(const TraceArgs& a, RayState& R, CellCache& C) {
     eval_grad<KIND>(a.g, R.nfg, R.te, C, O, h * (pxf + hh * F2x), h * (pyf + hh * F2y), h * (pzf + hh * F2z), ne, gx,
                     gy, gz);
     tx += gx; ty += gy; tz += gz;
+    if (TAPE && tp) {
+      tp[kTapeS * ts] = sx; tp[(kTapeS + 1) * ts] = sy; tp[(kTapeS + 2) * ts] = sz;
+      tp[kTapeT * ts] = tx; tp[(kTapeT + 1) * ts] = ty; tp[(kTapeT + 2) * ts] = tz;
+    }
     // RK4: dr = h p + h^2/6 (F1 + F2 + F3), dp = h/6 (F1 + 2 F2 + 2 F3 + F4),
     // F = -1/2 Xf grad n_e, the coefficient applied in FP64.
     const double c6 = R.cfd * hd * (1.0 / 6.0);
@@ -635,16 +676,17 @@ __device__ int ray_step(const TraceArgs& a, RayState& R, CellCache& C) {
 
   // Eq. 5: chord direction (the chord is exactly the increment dr).
   const Real dx = Real(drx), dy = Real(dry), dz = Real(drz);
-  const Real ds = sqrt(dx * dx + dy * dy + dz * dz);
+  const Real ds2 = dx * dx + dy * dy + dz * dz;
+  const Real inv_ds = rsqrt_r(ds2);
+  const Real ds = ds2 * inv_ds;
   float lnM = 0.0f;
   if (mag) {
-    const Real inv_ds = Real(1) / ds;
     const Real tx = dx * inv_ds, ty = dy * inv_ds, tz = dz * inv_ds;
     // Eq. 6: a = z unless |t_z| is near 1, then y; e1 = a x t / |a x t|, e2 = t x e1.
     Real c1x, c1y, c1z;
     if (fabs(tz) > Real(0.9)) { c1x = tz; c1y = Real(0); c1z = -tx; }
     else { c1x = -ty; c1y = tx; c1z = Real(0); }
-    const Real ci = Real(1) / sqrt(c1x * c1x + c1y * c1y + c1z * c1z);
+    const Real ci = rsqrt_r(c1x * c1x + c1y * c1y + c1z * c1z);
     const Real e1x = c1x * ci, e1y = c1y * ci, e1z = c1z * ci;
     const Real eps = Real(a.eta) * ds;  // Eq. 8
     // Eqs. 7 and 9 in difference form: the perturbed ray starts at r_i + eps e_j with
@@ -667,12 +709,18 @@ __device__ int ray_step(const TraceArgs& a, RayState& R, CellCache& C) {
       eval_grad<KIND>(a.g, R.nfg, R.te, C, O, d3x + fx + hq * q1x, d3y + fy + hq * q1y, d3z + fz + hq * q1z, ne, gx,
                       gy, gz);
       ax += R.cf * gx - F3x; ay += R.cf * gy - F3y; az += R.cf * gz - F3z;
+      if (TAPE && tp) {
+        float* q = tp + size_t(kTapeQ + 3 * jj) * ts;
+        q[0] = q1x; q[ts] = q1y; q[2 * ts] = q1z;
+        float* f = tp + size_t(kTapeA + 3 * jj) * ts;
+        f[0] = ax; f[ts] = ay; f[2 * ts] = az;
+      }
       const Real sx = d0x + Real(hh6 * ax), sy = d0y + Real(hh6 * ay), sz = d0z + Real(hh6 * az);
       if (jj == 0) { s1x = sx; s1y = sy; s1z = sz; }
       else det = (s1y * sz - s1z * sy) * tx + (s1z * sx - s1x * sz) * ty + (s1x * sy - s1y * sx) * tz;
     }
     // Eqs. 10-11: M = |(dr1 x dr2) . t| / eps^2; ln M from the accurately formed M - 1.
-    const Real mm1 = fabs(det) / (eps * eps) - Real(1);
+    const Real mm1 = fabs(det) * rcp_r(eps * eps) - Real(1);
     lnM = fast_log1pf(float(mm1));
   }
 
@@ -696,11 +744,12 @@ __device__ int ray_step(const TraceArgs& a, RayState& R, CellCache& C) {
   const float hl = 0.5f * float(lam);
   float ne_m, te_m;
   eval_value<KIND>(a.g, R.nfg, R.te, C, O, hl * float(drx), hl * float(dry), hl * float(drz), ne_m, te_m);
+  if (TAPE && tp) { tp[kTapeNeM * ts] = ne_m; tp[kTapeTeM * ts] = te_m; }
   Real dtau = Real(0);
   if (!(a.flags & RT_TEST_NO_ABSORPTION)) {
     const float lt = __builtin_amdgcn_logf(te_m) * 0.69314718056f;
     const float lnl = (te_m >= 2.0e5f) ? 24.5f + lt - R.lnf : 18.2f + 1.5f * lt - R.lnf;
-    const float kn = kFFCoefF * ne_m * ne_m * lnl * rcpf(R.f2 * te_m * sqrtf(te_m));
+    const float kn = kFFCoefF * ne_m * ne_m * lnl * rcpf(R.f2 * te_m * sqrt_fast(te_m));
     dtau = Real(kn) * Real(kRsunCm * lam * hd);
   }
   const Real gamma = -Real(lam) * Real(lnM);
@@ -732,7 +781,7 @@ __device__ int ray_step(const TraceArgs& a, RayState& R, CellCache& C) {
   }
   index_advance<KIND>(a.g, R, drx, dry, drz);
   R.rx = nx; R.ry = ny; R.rz = nz;
-  R.rmin = fminf(R.rmin, float(sqrt(r1sq)));
+  R.rmin = fminf(R.rmin, sqrt_fast(float(r1sq)));
   return kRunning;
 }
 

@@ -231,6 +231,23 @@ def trace_maps(models, freqs, image, prm, *, info=True, stats=True, path_rays=No
     return res
 
 
+def capture_trace_maps(models, freqs, image, prm, *, info=False, stats=True):
+    """Capture one rt_trace_maps call (no path output) in a HIP graph.
+
+    Returns (graph, out): `graph.replay()` re-runs the whole call (counter and
+    statistics fills, the launch table and the trace kernels) into the tensors
+    of `out`.  A warm-up call first sizes the library's per-call tables, so the
+    captured call allocates nothing and only launches kernels on the capture
+    stream (every clear is a fill kernel, no memset node)."""
+    import torch
+    out = trace_maps(models, freqs, image, prm, info=info, stats=stats)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        trace_maps(models, freqs, image, prm, info=info, stats=stats, out=out)
+    return graph, out
+
+
 def trace_adjoint(model, freqs, image, prm, weights, *, tb=True, stream=None, out=None):
     """Reverse mode of the forward maps of one model: loss = sum w T_b and its
     gradient w.r.t. ln n_e and ln T of every vertex.  `weights` is a float32

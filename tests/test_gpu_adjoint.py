@@ -262,3 +262,37 @@ def test_autograd_function_backward_is_the_adjoint(R):
                                atol=1e-6 * np.abs(ref["grad_ln_te"].cpu().numpy()).max())
     np.testing.assert_array_equal(tb.detach().cpu().numpy(), ref["tb"].cpu().numpy())
     m.close()
+
+
+def test_gradient_agrees_with_central_differences(R, orc, small):
+    """The GPU gradient against central finite differences of the FP64 loss
+    (oracle forward) on the vertices with the largest gradients: h = 1e-5 in ln,
+    divided by the realized ln-difference after FP32 rounding of e^{+-h} x value.
+    (h = 1e-3 spans kinks of the piecewise-smooth discrete map on some vertices.)"""
+    cor, m = small
+    freqs = np.array([80e6])
+    nu = 8
+    kw = dict(ds_max=0.01, n_floor=0.1, max_steps=200000)
+    w = np.zeros((1, nu, nu), np.float32)
+    w.flat[[10, 27, 36, 45]] = np.array([0.9, 0.6, 0.8, 0.7], np.float32)
+    print("case adjoint vs central differences", flush=True)
+    _, gne, gte, _ = _run(R, m, freqs, R.image_desc(nu, 2.0), R.params(**kw), w)
+    P = orc.make_params(**kw)
+    im_o = orc.make_image(nu, 2.0)
+    h = 1e-5
+    for which, g, k in (("ne", gne, 3), ("te", gte, 2)):
+        for flat in np.argsort(-np.abs(g).ravel())[:k]:
+            vals = []
+            for sgn in (1, -1):
+                arr = (cor.ne if which == "ne" else cor.te).ravel().copy()
+                x0 = np.float64(arr[flat])
+                arr[flat] = np.float32(x0 * math.exp(sgn * h))
+                ln_d = math.log(np.float64(arr[flat]) / x0)
+                ne = arr.reshape(cor.shape) if which == "ne" else cor.ne
+                te = arr.reshape(cor.shape) if which == "te" else cor.te
+                c2 = corona.Corona(cor.nr, cor.nt, cor.nph, cor.r_in, cor.r_max, ne, te)
+                loss, _ = orc.dual_loss(orc.OracleMedium.from_corona(c2), P, im_o, freqs, w)
+                vals.append((loss, ln_d))
+            fd = (vals[0][0] - vals[1][0]) / (vals[0][1] - vals[1][1])
+            print(f"  {which} vertex {int(flat)}: gpu {g.ravel()[flat]:.6e} fd {fd:.6e}", flush=True)
+            assert float(g.ravel()[flat]) == pytest.approx(fd, rel=1e-4), (which, int(flat))

@@ -193,3 +193,29 @@ def test_structured_workload_full_size_sampled(R, orc):
     assert flagged < 0.1 * len(pix) * len(wl.freqs)
     m.close()
     torch.cuda.empty_cache()
+
+
+def test_graph_replay_equals_eager(R, structured_small):
+    """A captured trace call replayed several times, with eager work and
+    synchronizations between replays, gives the eager maps every time."""
+    import torch
+    cor, m = structured_small
+    freqs = [60e6, 240e6]
+    im = R.image_desc(48, 2.5)
+    prm = R.params(ds_max=0.01, n_floor=0.1)
+    print("case graph replay", flush=True)
+    eager = R.trace_maps([m], freqs, im, prm, info=False, stats=True)
+    torch.cuda.synchronize()
+    ref = eager["tb"].clone()
+    ref_stats = R.decode_stats(eager["stats"])
+    graph, out = R.capture_trace_maps([m], freqs, im, prm)
+    for k in range(4):
+        out["tb"].fill_(-1.0)
+        junk = torch.randn(1 << 16, device="cuda").sum()  # eager work between replays
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out["tb"], ref), k
+        st = R.decode_stats(out["stats"])
+        assert st["ray_steps"] == ref_stats["ray_steps"], k
+        assert float(junk) == float(junk)
