@@ -29,11 +29,11 @@ namespace rt {
 // ---------------------------------------------------------------------------
 // Channel adjoints.  A model evaluation's adjoint is first written to a per-lane
 // log entry (cell key, cell fractions, one adjoint per channel); after a run of
-// evaluations the log is replayed: entries of one cell are summed per corner in
-// registers and added to the lane's cell accumulator in LDS (channel ch of
-// corner k at v[(kGradChannels k + ch) * kWaveLanes]), which is flushed with
-// FP64 atomics into the per-vertex accumulator when the lane moves to another
-// cell.
+// evaluations the log is replayed: entries are summed per corner in registers
+// and added to the lane's cell accumulator in LDS (channel ch of corner k at
+// v[(kGradChannels k + ch) * kWaveLanes]).  When the lane moves to another cell
+// the accumulator keeps the corners the two cells share and sends the others to
+// the per-vertex FP64 accumulator with atomics.
 // ---------------------------------------------------------------------------
 struct GradAcc {
   int key;   // packed index of the cell's corner 0, or -1 when empty
@@ -53,74 +53,110 @@ __device__ __forceinline__ void log_entry(float* lg, int e, const Loc& L, float 
   p[7 * kWaveLanes] = c3; p[8 * kWaveLanes] = c4;
 }
 
-// Move the lane's LDS accumulator to cell `key`: the old cell's nonzero channel
-// adjoints go to gacc with FP64 atomics and the new cell starts from s.
+// Move the lane's LDS accumulator to cell `key` (-1: empty it).  Corners shared
+// with the old cell (a move by one cell along one axis shares four) keep their
+// sums; the old cell's other nonzero channel adjoints go to gacc with FP64
+// atomics; then s is added.
 __device__ __forceinline__ void acc_replace(const DevGeom& g, GradAcc& A, double* gacc, int key,
                                             const float s[8][kGradChannels]) {
+  float old[8][kGradChannels];
+#pragma unroll
+  for (int k = 0; k < 8; ++k)
+#pragma unroll
+    for (int ch = 0; ch < kGradChannels; ++ch) old[k][ch] = A.v[(k * kGradChannels + ch) * kWaveLanes];
+  const int s1 = g.n2p, s0 = g.n1 * g.n2p;
+  // axis bit b and direction of a unit move (0: none)
+  int b = 0, dir = 0;
+  if (A.key >= 0 && key >= 0) {
+    const int D = key - A.key;
+    if (D == 1 || D == -1) { b = 1; dir = D; }
+    else if (D == s1 || D == -s1) { b = 2; dir = D > 0 ? 1 : -1; }
+    else if (D == s0 || D == -s0) { b = 4; dir = D > 0 ? 1 : -1; }
+  }
   if (A.key >= 0) {
-    const int s1 = g.n2p, s0 = g.n1 * g.n2p;
     // a key always names a cell whose far corner lies inside the packed grid
     const bool inside = (long long)A.key + s0 + s1 + 1 < (long long)g.n0 * s0;
-    float old[8][kGradChannels];
-#pragma unroll
-    for (int k = 0; k < 8; ++k)
-#pragma unroll
-      for (int ch = 0; ch < kGradChannels; ++ch) old[k][ch] = A.v[(k * kGradChannels + ch) * kWaveLanes];
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
+      // old corner k survives when the move goes towards its side of the cell
+      const bool keep = dir != 0 && (((k & b) != 0) == (dir > 0));
       const int off = ((k & 4) ? s0 : 0) + ((k & 2) ? s1 : 0) + (k & 1);
       double* dst = gacc + size_t(A.key + off) * kGradChannels;
 #pragma unroll
       for (int ch = 0; ch < kGradChannels; ++ch)
-        if (inside && old[k][ch] != 0.0f) unsafeAtomicAdd(dst + ch, double(old[k][ch]));
+        if (!keep && inside && old[k][ch] != 0.0f) unsafeAtomicAdd(dst + ch, double(old[k][ch]));
     }
   }
+  // new corner k is old corner ko when the two cells share that vertex (the
+  // old sums are read back from LDS, which still holds them, by address)
+  float nv[8][kGradChannels];
 #pragma unroll
-  for (int k = 0; k < 8; ++k)
+  for (int k = 0; k < 8; ++k) {
+    const bool shared = dir != 0 && (((k & b) != 0) == (dir < 0));
+    const int ko = dir > 0 ? (k | b) : (k & ~b);
 #pragma unroll
-    for (int ch = 0; ch < kGradChannels; ++ch) A.v[(k * kGradChannels + ch) * kWaveLanes] = s[k][ch];
+    for (int ch = 0; ch < kGradChannels; ++ch)
+      nv[k][ch] = s[k][ch] + (shared ? A.v[(ko * kGradChannels + ch) * kWaveLanes] : 0.0f);
+  }
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+#pragma unroll
+    for (int ch = 0; ch < kGradChannels; ++ch) A.v[(k * kGradChannels + ch) * kWaveLanes] = nv[k][ch];
+  }
   A.key = key;
 }
 
-__device__ __forceinline__ void acc_commit(const DevGeom& g, GradAcc& A, double* gacc, int key,
-                                           const float s[8][kGradChannels]) {
-  if (key == A.key) {
+__device__ __forceinline__ void acc_add(GradAcc& A, const float s[8][kGradChannels]) {
 #pragma unroll
-    for (int k = 0; k < 8; ++k)
+  for (int k = 0; k < 8; ++k)
 #pragma unroll
-      for (int ch = 0; ch < kGradChannels; ++ch) A.v[(k * kGradChannels + ch) * kWaveLanes] += s[k][ch];
-  } else {
-    acc_replace(g, A, gacc, key, s);
-  }
+    for (int ch = 0; ch < kGradChannels; ++ch) A.v[(k * kGradChannels + ch) * kWaveLanes] += s[k][ch];
 }
 
-// Replay log entries [0, n): consecutive entries of one cell are summed in
-// registers and committed to the accumulator once.
+// Replay log entries [0, n).  Entries of the accumulator's cell are summed in
+// registers (sa), entries of one other cell too (sb); after the loop sa is added
+// to the accumulator and a lane that met another cell moves its accumulator
+// there.  The moves (and their atomics) of all lanes thus happen at one point
+// of the program rather than wherever each lane meets a new cell; a third
+// cell within one replay takes the same move early.
 __device__ __forceinline__ void log_replay(const DevGeom& g, GradAcc& A, double* gacc, const float* lg, int n) {
-  float s[8][kGradChannels];
-  int gk = -1;
+  float sa[8][kGradChannels], sb[8][kGradChannels];
+#pragma unroll
+  for (int k = 0; k < 8; ++k)
+#pragma unroll
+    for (int ch = 0; ch < kGradChannels; ++ch) sa[k][ch] = sb[k][ch] = 0.0f;
+  int kb = -1;
 #pragma unroll 1
   for (int e = 0; e < n; ++e) {
     const float* p = lg + e * kLogWords * kWaveLanes;
     const int key = __float_as_int(p[0]);
-    if (key != gk) {
-      if (gk >= 0) acc_commit(g, A, gacc, gk, s);
-      gk = key;
+    if (key != A.key && key != kb) {
+      if (kb >= 0) {
+        acc_add(A, sa);
+        acc_replace(g, A, gacc, kb, sb);
 #pragma unroll
-      for (int k = 0; k < 8; ++k)
+        for (int k = 0; k < 8; ++k)
 #pragma unroll
-        for (int ch = 0; ch < kGradChannels; ++ch) s[k][ch] = 0.0f;
+          for (int ch = 0; ch < kGradChannels; ++ch) sa[k][ch] = sb[k][ch] = 0.0f;
+      }
+      kb = key;
     }
+    const bool in_a = key == A.key;
     float W[8];
     weights8(p[kWaveLanes], p[2 * kWaveLanes], p[3 * kWaveLanes], W);
 #pragma unroll
     for (int ch = 0; ch < kGradChannels; ++ch) {
       const float c = p[(4 + ch) * kWaveLanes];
+      const float ca = in_a ? c : 0.0f, cb = in_a ? 0.0f : c;
 #pragma unroll
-      for (int k = 0; k < 8; ++k) s[k][ch] = fmaf(W[k], c, s[k][ch]);
+      for (int k = 0; k < 8; ++k) {
+        sa[k][ch] = fmaf(W[k], ca, sa[k][ch]);
+        sb[k][ch] = fmaf(W[k], cb, sb[k][ch]);
+      }
     }
   }
-  if (gk >= 0) acc_commit(g, A, gacc, gk, s);
+  acc_add(A, sa);
+  if (kb >= 0) acc_replace(g, A, gacc, kb, sb);
 }
 
 // Flush the accumulator to gacc (end of the lane's work).

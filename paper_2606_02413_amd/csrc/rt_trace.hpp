@@ -64,12 +64,19 @@ __device__ __forceinline__ float fast_atan2f(float y, float x) {
   return copysignf(r, y);
 }
 
-// Angle of a small increment: atan2(y, x) for x > 0 and |y| <= tan(pi/8) x takes
-// the series after one reciprocal (no octant reduction); any other argument
-// goes through fast_atan2f.  The angular increments from a step's origin to its
-// evaluation points are this small except next to the polar axis.
+// Angle of a small increment: atan2(y, x) for x > 0 and |y| <= x / 10 is
+// t - t^3/3 + t^5/5 - t^7/7 with t = y / x (truncation below 1.2e-9 of the
+// angle); any other argument goes through fast_atan2f.  The angular increments
+// from a step's origin to its evaluation points are this small except next to
+// the polar axis.
 __device__ __forceinline__ float atan2_inc(float y, float x) {
-  if (x > 0.0f && fabsf(y) <= 0.41421356f * x) return atan_poly(y * rcpf(x));
+  if (x > 0.0f && fabsf(y) <= 0.1f * x) {
+    const float t = y * rcpf(x), t2 = t * t;
+    float s = -1.0f / 7.0f;
+    s = fmaf(s, t2, 1.0f / 5.0f);
+    s = fmaf(s, t2, -1.0f / 3.0f);
+    return fmaf(t * t2, s, t);
+  }
   return fast_atan2f(y, x);
 }
 
@@ -87,6 +94,19 @@ __device__ __forceinline__ float fast_log1pf(float z) {
     return 2.0f * w * s;
   }
   return __builtin_amdgcn_logf(1.0f + z) * 0.69314718056f;
+}
+
+// log1p for the small radius increments of the evaluation points: the series
+// to w^5 for |z| <= 1/20 (|w| <= 0.026, relative truncation below 1e-11),
+// fast_log1pf otherwise.
+__device__ __forceinline__ float log1p_inc(float z) {
+  if (fabsf(z) <= 0.05f) {
+    const float w = z * rcpf(2.0f + z);
+    const float w2 = w * w;
+    const float s = fmaf(fmaf(w2, 1.0f / 5.0f, 1.0f / 3.0f), w2, 1.0f);
+    return 2.0f * w * s;
+  }
+  return fast_log1pf(z);
 }
 
 // FP64 reciprocal: hardware estimate and two Newton steps.
@@ -263,13 +283,17 @@ __device__ __forceinline__ void cell_clamped(float x, int I, int n, int& a, floa
   else if (a > n - 2) { a = n - 2; u = 1.0f; held = true; }
 }
 
+// Periodic axis: the offset of an evaluation point from its step origin is an
+// angle in [-pi, pi], at most n/2 cells, so one wrap in either direction brings
+// the cell into [0, n); anything else (a non-finite offset) is sent to cell 0.
 __device__ __forceinline__ void cell_periodic(float x, int I, int n, int& c, float& w) {
   float fk = floorf(x);
   if (!(fk >= -1.0e9f && fk <= 1.0e9f)) fk = 0.0f;
   w = x - fk;
   c = I + int(fk);
-  c = c % n;
-  if (c < 0) c += n;
+  if (c >= n) c -= n;
+  else if (c < 0) c += n;
+  if ((unsigned)c >= (unsigned)n) c = 0;
 }
 
 template <int KIND>
@@ -280,12 +304,14 @@ __device__ __forceinline__ void locate(const DevGeom& g, const StepOrigin& O, fl
     const float rd = O.x * dx + O.y * dy;
     const float dd = dx * dx + dy * dy;
     const float c = 2.0f * (rd + O.z * dz) + (dd + dz * dz);
-    x0 = O.f0 + 0.5f * fast_log1pf(c * O.inv_r2) * g.inv_dl;
+    x0 = O.f0 + 0.5f * log1p_inc(c * O.inv_r2) * g.inv_dl;
     // azimuth: angle from (x_i, y_i) to (x_i + dx, y_i + dy)
     x2 = O.f2 + atan2_inc(O.x * dy - O.y * dx, O.rho2 + rd) * g.inv_dph;
     // colatitude: angle from (z_i, rho_i) to (z_q, rho_q) in the meridional plane
     const float e = 2.0f * rd + dd;
-    const float rhoq = sqrt_fast(fmaxf(O.rho2 + e, 0.0f));
+    const float m = fmaxf(O.rho2 + e, 0.0f);
+    const float rhoi = m > 1.0e-24f ? rsqrtf(m) : 0.0f;  // 0 on the polar axis (rho < 1e-12)
+    const float rhoq = m * rhoi;
     const float den = rhoq + O.rho;
     const float drho = den > 0.0f ? e * rcpf(den) : 0.0f;
     const float zq = O.z + dz;
@@ -293,7 +319,7 @@ __device__ __forceinline__ void locate(const DevGeom& g, const StepOrigin& O, fl
     L.rinv = rsqrtf(O.r2 + c);
     L.rho = rhoq;
     L.axis = rhoq < 1e-12f;
-    L.rhoinv = L.axis ? 0.0f : rcpf(rhoq);
+    L.rhoinv = L.axis ? 0.0f : rhoi;
     L.x = O.x + dx; L.y = O.y + dy; L.z = zq;
   } else {
     x0 = O.f0 + dx * g.inv_sp[0];
@@ -306,7 +332,8 @@ __device__ __forceinline__ void locate(const DevGeom& g, const StepOrigin& O, fl
   L.cl2 = false;
   if constexpr (KIND == RT_GRID_SPHERICAL_LOGR) cell_periodic(x2, O.i2, g.n2, c, L.w);
   else cell_clamped(x2, O.i2, g.n2, c, L.w, L.cl2);
-  L.key = (a * g.n1 + b) * g.n2p + c;
+  // cell indices and grid extents are below 2^24 and keys below 2^31: 24-bit multiplies
+  L.key = int(__umul24(__umul24(unsigned(a), unsigned(g.n1)) + unsigned(b), unsigned(g.n2p))) + c;
 }
 
 __device__ __forceinline__ void weights8(float u, float v, float w, float W[8]) {

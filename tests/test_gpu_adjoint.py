@@ -162,6 +162,47 @@ def test_gradient_matches_oracle_long_rays(R, orc):
     m.close()
 
 
+def test_gradient_matches_oracle_at_the_step_limit(R, orc, small):
+    """Every ray stops at max_steps = 37 inside the model (MAX_STEPS, no end
+    crossing), swept in chunks of K = 8 with a partial last chunk."""
+    cor, m = small
+    freqs = np.array([60e6, 250e6])
+    nu = 10
+    med = orc.OracleMedium.from_corona(cor)
+    kw = dict(ds_max=0.01, n_floor=0.1, max_steps=37)
+    im_o = orc.make_image(nu, 1.6)
+    flags = _oracle_flags(orc, med, orc.make_params(twin_check=True, **kw), im_o, freqs, nu * nu)
+    w = _weights((2, nu, nu), 1002, flags)
+    print("case adjoint max_steps", flush=True)
+    lo, gne_o, gte_o = orc.grad_loss(med, orc.make_params(**kw), im_o, freqs, w)
+    prm = R.params(checkpoint_every=8, **kw)
+    im = R.image_desc(nu, 1.6)
+    fwd = R.trace_maps([m], freqs, im, prm, info=True, stats=False)
+    info = R.decode_info(fwd["info"][0]).reshape(-1)
+    assert np.all(info["n_steps"] == 37) and np.all(info["code"] == R.MAX_STEPS)
+    loss, gne, gte, _ = _run(R, m, freqs, im, prm, w)
+    assert loss == pytest.approx(lo, rel=1e-5)
+    _compare_grad("max_steps ln_ne", gne, gne_o)
+    _compare_grad("max_steps ln_te", gte, gte_o)
+
+
+def test_zero_weights_and_missing_rays(R, small):
+    """w = 0 everywhere: no ray is swept, the gradient is exactly zero and the
+    loss is zero.  An image entirely outside r_max: every ray misses, loss =
+    sum w T_sky, gradient zero."""
+    cor, m = small
+    freqs = np.array([100e6])
+    print("case adjoint zero weights / misses", flush=True)
+    loss, gne, gte, tb = _run(R, m, freqs, R.image_desc(12, 2.0), R.params(ds_max=0.01, n_floor=0.1),
+                              np.zeros((1, 12, 12), np.float32))
+    assert loss == 0.0 and not gne.any() and not gte.any() and np.all(tb > 0)
+    # 2 x 2 pixels over +/-8 R_sun: centres at (+/-4, +/-4), impact 5.66 > r_max = 5
+    prm = R.params(ds_max=0.01, n_floor=0.1, tb_sky=3.0)
+    loss, gne, gte, tb = _run(R, m, freqs, R.image_desc(2, 8.0), prm, np.ones((1, 2, 2), np.float32))
+    assert np.all(tb == np.float32(3.0)) and loss == pytest.approx(3.0 * 4, rel=1e-12)
+    assert not gne.any() and not gte.any()
+
+
 def _cartesian_model(n=28, lo=-3.0, seed=5):
     """Seeded input on a Cartesian lattice: Baumbach-Allen density times a smooth
     random modulation, temperature 1-2 MK (inputs only)."""
