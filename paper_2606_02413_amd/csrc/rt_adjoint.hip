@@ -7,19 +7,54 @@
 
 namespace rt {
 
-// A wave claims one 8x8 pixel tile of one frequency at a time from a global
-// counter; each lane runs the forward trace and the reverse sweep of its ray.
+// Tile of the batch -> (image, pixel) of a lane; false for a lane outside a
+// ragged image.
+__device__ __forceinline__ bool tile_pixel(const TraceArgs& a, int t, int lane, int& img, int& pix) {
+  img = t / a.tiles_per_image;
+  const int rem = t - img * a.tiles_per_image;
+  const int ty = rem / a.tiles_u, tx = rem - ty * a.tiles_u;
+  const int i = ty * kTile + (lane >> 3), j = tx * kTile + (lane & 7);
+  pix = i * a.nu + j;
+  return i < a.nv && j < a.nu;
+}
+
+// Forward pass of the adjoint: one wave per tile of the batch, one lane per ray,
+// two waves per SIMD like the forward kernels.  Per-ray checkpoints and the
+// sweep record go to the ray's column rid = 64 (tile - tile0) + lane.
+template <int KIND, int MODE>
+__global__ __launch_bounds__(256, 2) void k_adjoint_forward(AdjointArgs aa) {
+  __shared__ float4 lds_c[4][8][kWaveLanes];
+  __shared__ float lds_t[4][8][kWaveLanes];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int tl = blockIdx.x * 4 + wave;
+  double loss = 0.0;
+  if (tl < aa.n_tiles) {
+    CellCache C;
+    C.key = -1;
+    C.c = &lds_c[wave][0][lane];
+    C.t = &lds_t[wave][0][lane];
+    const int rid = tl * kWaveLanes + lane;
+    int img, pix;
+    if (tile_pixel(aa.t, aa.tile0 + tl, lane, img, pix)) adjoint_forward_ray<KIND, MODE>(aa, img, pix, rid, C, loss);
+    else aa.meta[rid] = 0;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) loss += __shfl_xor(loss, off);
+  if (lane == 0 && tl < aa.n_tiles) unsafeAtomicAdd(aa.loss, loss);
+}
+
+// Reverse sweeps: a wave claims one tile of the batch at a time from a global
+// counter; each lane sweeps its ray backward from the ray's checkpoints.
 // The tracing mode (line of sight, refraction, refraction with magnification)
 // is a template parameter: one kernel per mode, with no branch on the call's
-// flags anywhere in the per-ray code.
-// Checkpoints and the step buffer are indexed by the lane's global slot.
+// flags anywhere in the per-ray code.  The chunk record is indexed by the lane's
+// global slot.
 template <int KIND, int MODE>
 __global__ __launch_bounds__(256, 1) void k_adjoint(AdjointArgs aa) {
   __shared__ float4 lds_c[4][8][kWaveLanes];
   __shared__ float lds_t[4][8][kWaveLanes];
   __shared__ float lds_g[4][8 * kGradChannels][kWaveLanes];
   __shared__ float lds_log[4][kLogEntries * kLogWords][kWaveLanes];
-  const TraceArgs& a = aa.t;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int slot = blockIdx.x * blockDim.x + threadIdx.x;
   CellCache C;
@@ -31,22 +66,16 @@ __global__ __launch_bounds__(256, 1) void k_adjoint(AdjointArgs aa) {
   A.v = &lds_g[wave][0][lane];
   for (int k = 0; k < 8 * kGradChannels; ++k) A.v[k * kWaveLanes] = 0.0f;
   float* lg = &lds_log[wave][0][lane];
-  double loss = 0.0;
   for (;;) {
     unsigned t = 0;
     if (lane == 0) t = atomicAdd(aa.counter, 1u);
     t = (unsigned)__shfl((int)t, 0);
     if (t >= (unsigned)aa.n_tiles) break;
-    const int img = int(t) / a.tiles_per_image;
-    const int rem = int(t) - img * a.tiles_per_image;
-    const int ty = rem / a.tiles_u, tx = rem - (rem / a.tiles_u) * a.tiles_u;
-    const int i = ty * kTile + (lane >> 3), j = tx * kTile + (lane & 7);
-    if (i < a.nv && j < a.nu) adjoint_ray<KIND, MODE>(aa, img, i * a.nu + j, slot, C, A, lg, loss);
+    int img, pix;
+    if (tile_pixel(aa.t, aa.tile0 + int(t), lane, img, pix))
+      adjoint_reverse_ray<KIND, MODE>(aa, img, pix, int(t) * kWaveLanes + lane, slot, C, A, lg);
   }
-  grad_flush(a.g, A, aa.gacc);
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) loss += __shfl_xor(loss, off);
-  if (lane == 0) unsafeAtomicAdd(aa.loss, loss);
+  grad_flush(aa.t.g, A, aa.gacc);
 }
 
 // d channel(a') / d n_e(a) for the index-space central difference along a
@@ -100,6 +129,22 @@ static int grid_for(long long n, int threads) {
   if (b > 65536) b = 65536;
   if (b < 1) b = 1;
   return int(b);
+}
+
+template <int KIND>
+static hipError_t launch_adjoint_forward_kind(const AdjointArgs& a, hipStream_t s) {
+  const bool refr = (a.t.flags & RT_USE_REFRACTION) != 0;
+  const bool mag = refr && (a.t.flags & RT_USE_MAGNIFICATION) != 0;
+  const int blocks = (a.n_tiles + 3) / 4;
+  if (mag) hipLaunchKernelGGL((k_adjoint_forward<KIND, kModeFull>), dim3(blocks), dim3(256), 0, s, a);
+  else if (refr) hipLaunchKernelGGL((k_adjoint_forward<KIND, kModeNoMag>), dim3(blocks), dim3(256), 0, s, a);
+  else hipLaunchKernelGGL((k_adjoint_forward<KIND, kModeLos>), dim3(blocks), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_adjoint_forward(const AdjointArgs& a, hipStream_t s) {
+  if (a.t.g.kind == RT_GRID_SPHERICAL_LOGR) return launch_adjoint_forward_kind<RT_GRID_SPHERICAL_LOGR>(a, s);
+  return launch_adjoint_forward_kind<RT_GRID_CARTESIAN>(a, s);
 }
 
 template <int KIND>

@@ -684,55 +684,74 @@ __device__ __forceinline__ void state_copy(double* buf, int from, int to, int li
   for (int f = 0; f < kCkptFields; ++f) dst[f * s] = src[f * s];
 }
 
-// One ray: the forward trace with checkpoints every kr steps (kr starts at K
-// and doubles, with every other checkpoint dropped, whenever the ray outgrows
-// the checkpoint capacity), then the reverse sweep segment by segment: each
-// chunk of at most K steps is recomputed from its checkpoint, writing each
-// step's start state and forward record, and swept backward.  Adds w T_b to
-// `loss` and writes T_b.
+// Forward pass of one ray for the adjoint: the trace with its state
+// checkpointed every kr steps (kr starts at K and doubles, with every other
+// checkpoint dropped, whenever the ray outgrows the checkpoint capacity) in the
+// ray's own column rid of ckpt.  Adds w T_b to `loss`, writes T_b and the
+// ray's record for the sweep: the step count (0 when the ray is not swept:
+// a miss, a non-finite step or w = 0), the termination code and checkpoint
+// count, and kr.
 template <int KIND, int MODE>
-__device__ __forceinline__ void adjoint_ray(const AdjointArgs& aa, int img, int pix, int slot, CellCache& C, GradAcc& A, float* lg,
-                            double& loss) {
+__device__ __forceinline__ void adjoint_forward_ray(const AdjointArgs& aa, int img, int pix, int rid, CellCache& C,
+                                                    double& loss) {
   const TraceArgs& a = aa.t;
-  const int npx = a.nu * a.nv;
-  const int id = img * npx + pix;
+  const int id = img * (a.nu * a.nv) + pix;
   const double wgt = double(aa.weights[id]);
+  const size_t nr = size_t(aa.n_rays);
   RayState R;
   if (!init_ray(a, img, pix, R, C)) {
     loss += wgt * a.tb_sky;
+    aa.meta[rid] = 0;
     return;
   }
   const int K = aa.K;
-  const size_t ts = size_t(aa.n_slots);
   int kr = K, nc = 0, code;
   do {
     if (R.n % kr == 0) {
       if (nc == aa.ckpt_cap) {
-        for (int j = 1; j < nc / 2; ++j) state_copy(aa.ckpt, 2 * j, j, aa.ckpt_cap, aa.n_slots, slot);
+        for (int j = 1; j < nc / 2; ++j) state_copy(aa.ckpt, 2 * j, j, aa.ckpt_cap, aa.n_rays, rid);
         nc /= 2;
         kr *= 2;
       }
-      state_store(aa.ckpt, nc, aa.ckpt_cap, aa.n_slots, slot, R);
+      state_store(aa.ckpt, nc, aa.ckpt_cap, aa.n_rays, rid, R);
       ++nc;
     }
-    code = ray_step<true, KIND, MODE, true>(a, R, C, nullptr, ts);
+    code = ray_step<true, KIND, MODE, true>(a, R, C, nullptr, 0);
   } while (code == kRunning);
   finish_ray(a, R);
-  const int N = R.n;
   const double tbc = (code == kHit) ? a.tb_inner : a.tb_sky;
   const float trans = __builtin_amdgcn_exp2f(-1.44269504089f * float(R.lam_tot));
   loss += wgt * double(float(R.A + double(trans) * tbc));
-  if (code == kNonfinite || wgt == 0.0) return;
+  aa.meta[rid] = (code == kNonfinite || wgt == 0.0) ? 0 : R.n;
+  aa.meta[nr + rid] = code | (nc << 8);
+  aa.meta[2 * nr + rid] = kr;
+}
 
+// Reverse sweep of one ray, segment by segment from its checkpoints: each chunk
+// of at most K steps is recomputed from its checkpoint, writing each step's
+// start state and forward record into the lane's slot, and swept backward.
+template <int KIND, int MODE>
+__device__ __forceinline__ void adjoint_reverse_ray(const AdjointArgs& aa, int img, int pix, int rid, int slot,
+                                                    CellCache& C, GradAcc& A, float* lg) {
+  const TraceArgs& a = aa.t;
+  const size_t nr = size_t(aa.n_rays);
+  const int N = aa.meta[rid];
+  if (N <= 0) return;
+  const int code = aa.meta[nr + rid] & 0xff, nc = aa.meta[nr + rid] >> 8, kr = aa.meta[2 * nr + rid];
+  const double wgt = double(aa.weights[img * (a.nu * a.nv) + pix]);
+  RayState R;
+  if (!init_ray(a, img, pix, R, C)) return;  // (not reached: a swept ray is no miss)
+  const int K = aa.K;
+  const size_t ts = size_t(aa.n_slots);
   AdjState S;
   S.rbx = S.rby = S.rbz = 0.0;
   S.pbx = S.pby = S.pbz = 0.0;
-  S.I = tbc;
+  S.I = (code == kHit) ? a.tb_inner : a.tb_sky;
   for (int seg = nc - 1; seg >= 0; --seg) {
     const int s0 = seg * kr, s1 = min(N, s0 + kr);
     for (int c1 = s1; c1 > s0; c1 -= K) {
       const int c0 = max(s0, c1 - K);
-      state_load(aa.ckpt, seg, aa.ckpt_cap, aa.n_slots, slot, R);
+      state_load(aa.ckpt, seg, aa.ckpt_cap, aa.n_rays, rid, R);
       R.n = s0;
       // steps s0 .. c0-1 are only retraced; steps c0 .. c1-1 are recorded
       while (R.n < c1) {

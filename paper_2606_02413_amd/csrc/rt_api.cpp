@@ -5,6 +5,7 @@
 
 #include <atomic>
 #include <cmath>
+#include <algorithm>
 #include <cstdlib>
 #include <cstring>
 #include <mutex>
@@ -76,7 +77,8 @@ struct DeviceScratch {
   size_t adj_bytes = 0;
   int n_cu = 0;
 };
-constexpr long long kAdjMaxCheckpoints = 128;  // per ray slot; longer rays thin their checkpoints
+constexpr long long kAdjMaxCheckpoints = 128;  // per ray; longer rays thin their checkpoints
+constexpr long long kAdjCheckpointBudget = 8ll << 30;  // bytes of per-ray checkpoints per batch of tiles
 constexpr unsigned kCounterSlots = 1024;
 std::mutex g_scratch_mu;
 DeviceScratch g_scratch[64];
@@ -563,18 +565,26 @@ rt_status rt_trace_adjoint(const rt_model* model, const double* freq_hz, int32_t
     if (cap < 2) cap = 2;
     cap += cap & 1;  // even: thinning keeps every other checkpoint
     const int n_tiles = a.tiles_per_image * n_freq;
+    // checkpoints are kept per ray: the tiles are traced and swept in batches
+    // whose checkpoints fit the budget
+    const long long tile_bytes = (long long)kWaveLanes * (cap * kCkptFields * (long long)sizeof(double) + 3 * 4);
+    long long batch = kAdjCheckpointBudget / tile_bytes;
+    if (batch < 1) batch = 1;
+    if (batch > n_tiles) batch = n_tiles;
     long long blocks = (long long)sc->n_cu * adjoint_blocks_per_cu(a.g.kind);
-    const long long max_useful = (n_tiles + 3) / 4;
+    const long long max_useful = (batch + 3) / 4;
     if (blocks > max_useful) blocks = max_useful;
     if (blocks < 1) blocks = 1;
     const long long n_slots = blocks * 256;
-    const size_t ck_bytes = size_t(cap) * kCkptFields * size_t(n_slots) * sizeof(double);
+    const long long n_rays = batch * kWaveLanes;
+    const size_t ck_bytes = size_t(cap) * kCkptFields * size_t(n_rays) * sizeof(double);
+    const size_t meta_bytes = size_t(3) * size_t(n_rays) * sizeof(int);
     const size_t st_bytes = size_t(K) * kCkptFields * size_t(n_slots) * sizeof(double);
     const size_t tp_bytes = size_t(K) * kTapeFields * size_t(n_slots) * sizeof(float);
     const long long nvp = (long long)a.g.n0 * a.g.n1 * a.g.n2p;
     const size_t acc_bytes = size_t(nvp) * kGradChannels * sizeof(double);
     const size_t tb_bytes = tb_out ? 0 : size_t(npx) * size_t(n_freq) * sizeof(float);
-    const size_t need = ck_bytes + st_bytes + tp_bytes + acc_bytes + tb_bytes + 256 * 4;
+    const size_t need = ck_bytes + meta_bytes + st_bytes + tp_bytes + acc_bytes + tb_bytes + 256 * 4;
     char* ws = nullptr;
     {
       std::lock_guard<std::mutex> lk(g_scratch_mu);
@@ -594,6 +604,7 @@ rt_status rt_trace_adjoint(const rt_model* model, const double* freq_hz, int32_t
     aa.ckpt = reinterpret_cast<double*>(ws + off); off += ck_bytes;
     aa.steps = reinterpret_cast<double*>(ws + off); off += st_bytes;
     aa.tape = reinterpret_cast<float*>(ws + off); off += tp_bytes;
+    aa.meta = reinterpret_cast<int*>(ws + off); off += (meta_bytes + 255) / 256 * 256;
     float* tb = tb_out ? tb_out : reinterpret_cast<float*>(ws + off);
     a.tb = tb;
     a.info = nullptr;
@@ -601,15 +612,20 @@ rt_status rt_trace_adjoint(const rt_model* model, const double* freq_hz, int32_t
     aa.t = a;
     aa.weights = weights;
     aa.loss = loss_out;
-    aa.counter = next_counters(sc);
     aa.K = K;
     aa.ckpt_cap = int(cap);
     aa.n_slots = int(n_slots);
-    aa.n_tiles = n_tiles;
     st = hip_check(launch_fill_u32(reinterpret_cast<unsigned*>(aa.gacc), 0u, (long long)(acc_bytes / 4), s), "gradient fill");
     if (st == RT_OK) st = hip_check(launch_fill_u32(reinterpret_cast<unsigned*>(loss_out), 0u, 2, s), "loss fill");
-    if (st == RT_OK) st = hip_check(launch_fill_u32(aa.counter, 0u, 1, s), "counter fill");
-    if (st == RT_OK) st = hip_check(launch_adjoint(aa, int(blocks), s), "adjoint launch");
+    for (int t0 = 0; st == RT_OK && t0 < n_tiles; t0 += int(batch)) {
+      aa.tile0 = t0;
+      aa.n_tiles = int(std::min<long long>(batch, n_tiles - t0));
+      aa.n_rays = aa.n_tiles * kWaveLanes;
+      aa.counter = next_counters(sc);
+      st = hip_check(launch_fill_u32(aa.counter, 0u, 1, s), "counter fill");
+      if (st == RT_OK) st = hip_check(launch_adjoint_forward(aa, s), "adjoint forward launch");
+      if (st == RT_OK) st = hip_check(launch_adjoint(aa, int(blocks), s), "adjoint launch");
+    }
     if (st == RT_OK)
       st = hip_check(launch_unpack_grad(a.g, model->nfg, model->te, aa.gacc, grad_ln_ne, grad_ln_te, s), "gradient gather");
     return st;

@@ -11,6 +11,7 @@ namespace rt {
 constexpr int kMaxModels = 16;    // models per persistent launch
 constexpr int kMaxFreqs = 128;    // frequencies per persistent launch
 constexpr int kTile = 8;          // 8 x 8 pixels per wave64
+constexpr int kWaveLanes = 64;
 constexpr int kXcds = 8;          // MI355X: 8 accelerator complex dies, blocks dealt round-robin
 constexpr int kPathStride = 9;    // x y z s lnM dlnS/ds tau ne te
 
@@ -64,8 +65,8 @@ struct TraceArgs {
   int refill_min_idle;        // a wave refills once at least this many lanes are idle (1..64)
 };
 
-// Reverse-mode (adjoint) launch over one model: the forward trace of every ray
-// with checkpoints, then its reverse sweep.
+// Reverse-mode (adjoint) launches over one model, per batch of tiles: the
+// forward trace of every ray with checkpoints, then the reverse sweeps.
 constexpr int kCkptFields = 10;   // r (3), p (3), grid index (3), optical depth so far
 constexpr int kGradChannels = 5;  // per vertex: n_e, the three index-space gradient channels, T
 // Per-step record of the forward quantities the reverse sweep needs (FP32):
@@ -80,11 +81,14 @@ struct AdjointArgs {
   const float* weights;       // [n_freq][nv][nu]
   double* loss;               // device scalar, accumulated
   double* gacc;               // [n0 * n1 * n2p][kGradChannels] channel adjoints, zeroed before launch
-  double* ckpt;               // [ckpt_cap][kCkptFields][n_slots]
+  double* ckpt;               // [ckpt_cap][kCkptFields][n_rays] checkpoints of the batch's rays
+  int* meta;                  // [3][n_rays] per ray: steps to sweep (0: none), code | checkpoints << 8, interval
   double* steps;              // [K][kCkptFields][n_slots] start state of each step of a chunk
   float* tape;                // [K][kTapeFields][n_slots] forward record of each step of a chunk
-  unsigned* counter;          // tile claim counter, zeroed before launch
-  int K, ckpt_cap, n_slots, n_tiles;
+  unsigned* counter;          // tile claim counter of the sweep, zeroed before launch
+  int K, ckpt_cap, n_slots;
+  int tile0, n_tiles;         // the batch: tiles tile0 .. tile0 + n_tiles - 1 (8x8 pixels of one frequency)
+  int n_rays;                 // 64 n_tiles; ray rid = 64 (tile - tile0) + lane
 };
 
 // Launchers (rt_kernels.hip).
@@ -97,6 +101,7 @@ hipError_t launch_start_index(const TraceArgs& a, double* out, float* ne_out, hi
 int persistent_blocks_per_cu(bool mixed, int kind);
 
 // Launchers (rt_adjoint.hip).
+hipError_t launch_adjoint_forward(const AdjointArgs& a, hipStream_t s);
 hipError_t launch_adjoint(const AdjointArgs& a, int blocks, hipStream_t s);
 hipError_t launch_unpack_grad(const DevGeom& g, const float4* nfg, const float* te, const double* gacc,
                               float* grad_ln_ne, float* grad_ln_te, hipStream_t s);

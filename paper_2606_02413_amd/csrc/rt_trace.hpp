@@ -194,7 +194,6 @@ __device__ __noinline__ double lib_atan2(double y, double x) { return atan2(y, x
 // conflicts).  Each lane only reads its own slots, which it wrote itself; LDS
 // operations of a wave complete in order.
 // ---------------------------------------------------------------------------
-constexpr int kWaveLanes = 64;
 struct CellCache {
   int key;
   float4* c;  // LDS, corner k at c[k * kWaveLanes]
