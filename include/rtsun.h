@@ -24,6 +24,10 @@
  *    not errors.
  *  - The caller owns every input and output buffer.  The library owns an
  *    rt_model's device copy until rt_model_free, and its own scratch.
+ *  - Trace calls on one device share that device's scratch (per-pixel launch
+ *    table, work counters, adjoint workspace): calls that could run at the
+ *    same time on different streams of one device race.  Issue them on one
+ *    stream, or synchronise between them.
  */
 #ifndef RTSUN_H
 #define RTSUN_H
@@ -199,11 +203,14 @@ rt_status rt_trace_maps(const rt_model* const* models, int32_t n_models, const d
  * checkpoints doubles its interval.  The reverse sweep recomputes each chunk of
  * steps from its checkpoint, recording every step's start state and the model
  * values its adjoint needs (188 bytes a step), and then sweeps the chunk
- * backward from that record.  Channel adjoints are accumulated per lane and cell
- * in FP32 and added into an FP64 per-vertex accumulator with atomics, so the
- * last bits can vary between runs.  Mixed precision only: RT_PREC_ALL_FP32,
- * RT_DETERMINISTIC_GRAD and RT_TEST_NO_ABSORPTION return RT_E_UNSUPPORTED.  The library keeps a
- * per-device workspace (checkpoints, chunk record, accumulator), grown on demand.
+ * backward from that record.  The image tiles (8 x 8 pixels of one frequency)
+ * are traced and swept in batches whose checkpoints (up to 10 KB a ray) fit an
+ * 8 GiB budget.  Channel adjoints are accumulated per lane and cell in FP32 and
+ * added into an FP64 per-vertex accumulator with atomics, so the last bits can
+ * vary between runs.  Mixed precision only: RT_PREC_ALL_FP32,
+ * RT_DETERMINISTIC_GRAD and RT_TEST_NO_ABSORPTION return RT_E_UNSUPPORTED.  The
+ * library keeps a per-device workspace (checkpoints, chunk records,
+ * accumulator), grown on demand and kept until the process ends.
  * Errors: RT_E_INVALID_ARG for NULL or inconsistent arguments, RT_E_CAPACITY,
  * RT_E_OUT_OF_MEMORY, RT_E_DEVICE; nothing is written on a validation error. */
 rt_status rt_trace_adjoint(const rt_model* model, const double* freq_hz, int32_t n_freq,
