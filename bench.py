@@ -63,6 +63,10 @@ def parse():
     ap.add_argument("--no-plain", action="store_true", help="skip the plain per-frequency timing")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint / forward timing")
+    ap.add_argument("--autotune-freqs", type=int, default=4,
+                    help="frequencies in the autotuner's sample of the workload (0: no autotuning, defaults)")
+    ap.add_argument("--tuning", default=None,
+                    help="fixed launch tuning refill_min_idle,blocks_per_cu,xcd_bands instead of autotuning")
     ap.add_argument("--adjoint-only", action="store_true",
                     help="only run the adjoint / forward timing on the adjoint workload (for profiling)")
     ap.add_argument("--batching", action="store_true",
@@ -282,7 +286,7 @@ def batching_study():
     span = {"plain_ms": p_ms, "ray_steps": steps, "max_steps": int(st["max_steps"]),
             "mean_steps_per_traced_ray": steps / max(1, int(r1["tb"].numel()) - int(st["code_count"][3]))}
     for thr in (64, 32, 8, 1):
-        os.environ["RT_REFILL_MIN_IDLE"] = str(thr)
+        R.set_tuning(R.tuning(refill_min_idle=thr), mdl.device)
         r2 = R.trace_maps([mdl], freqs, im, R.params(**kw), info=False, stats=False)
         torch.cuda.synchronize()
         ms = timed(lambda: R.trace_maps([mdl], freqs, im, R.params(**kw), info=False, stats=False, out=r2))
@@ -291,7 +295,7 @@ def batching_study():
         span[f"bitwise_equal_refill{thr}"] = bool(torch.equal(r2["tb"], r1["tb"]))
         progress(f"long-span refill {thr}: {ms:.0f} ms (plain {p_ms:.0f})")
         del r2
-    os.environ.pop("RT_REFILL_MIN_IDLE", None)
+    R.set_tuning(R.tuning(), mdl.device)
     out["long_span_variant"] = span
     print(json.dumps(out), flush=True)
     mdl.close()
@@ -333,6 +337,24 @@ def main():
     def run(plain, out=None):
         prm = R.params(ds_max=wl.ds_max, n_floor=wl.n_floor, max_steps=wl.max_steps, plain=plain)
         return R.trace_maps([model], wl.freqs, im, prm, info=False, stats=True, out=out)
+
+    # launch tuning of the persistent trace (result-invariant): autotuned on a
+    # sample of the workload unless fixed on the command line
+    tune_info = None
+    if args.tuning:
+        rf, bpc, bands = (int(x) for x in args.tuning.split(","))
+        R.set_tuning(R.tuning(rf, bpc, bands), model.device)
+        tune_info = {"tuning": R.get_tuning(model.device).as_dict(), "source": "command line"}
+    elif args.autotune_freqs > 0:
+        prm_t = R.params(ds_max=wl.ds_max, n_floor=wl.n_floor, max_steps=wl.max_steps)
+        t0 = time.perf_counter()
+        res = R.autotune([model], wl.freqs, im, prm_t, max_freqs=args.autotune_freqs)
+        tune_info = {"tuning": res["tuning"], "source": f"autotuned on {args.autotune_freqs} of the frequencies",
+                     "sample_best_ms": round(res["best_ms"], 3), "sample_default_ms": round(res["default_ms"], 3),
+                     "tuner_s": round(time.perf_counter() - t0, 2)}
+        progress(f"autotune: {tune_info}")
+    else:
+        tune_info = {"tuning": R.get_tuning(model.device).as_dict(), "source": "defaults"}
 
     # batched persistent launch (the production path)
     out = run(False)
@@ -402,7 +424,7 @@ def main():
                    "global_batch": wl.n_pix * wl.n_pix * maps_per_step, "ray_steps_per_step": steps_per_pass},
         "maps_8freq_per_s": 1000.0 / ms_per_step,
         "maps_per_s": maps_per_step * 1000.0 / ms_per_step,
-        "batched": {"ms_per_step": ms_per_step, "ray_steps_per_s": rate},
+        "batched": {"ms_per_step": ms_per_step, "ray_steps_per_s": rate, "launch_tuning": tune_info},
         "plain": plain,
         "batched_over_plain": (plain["ms_per_step"] / ms_per_step) if plain else None,
         "adjoint_fwd_ratio": adjoint["ratio"] if adjoint else None,

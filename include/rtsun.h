@@ -163,6 +163,44 @@ typedef struct {
   unsigned int _pad;
 } rt_trace_stats;                 /* 40 bytes */
 
+/* Launch tuning of the persistent (batched) trace.  Every setting gives
+ * bitwise-identical maps: each lane traces its own ray with the same
+ * arithmetic, only the order in which rays are taken up changes.
+ *  refill_min_idle: a wave takes up new rays once at least this many of its
+ *    64 lanes are idle (1..64; 64 = whole waves only).
+ *  blocks_per_cu: 256-thread blocks per compute unit (0 = the most that fit).
+ *  xcd_bands: 8 = the tiles are split into 8 contiguous bands of image rows,
+ *    one per die, each with its own claim counter (waves of a die start in
+ *    their band and take from the others when it is empty); 1 = one queue. */
+typedef struct {
+  uint32_t abi_version;     /* RT_ABI_VERSION */
+  int32_t refill_min_idle;
+  int32_t blocks_per_cu;
+  int32_t xcd_bands;
+} rt_tuning;
+
+/* Defaults: refill_min_idle 64, blocks_per_cu 0, xcd_bands 8. */
+void rt_tuning_default(rt_tuning* t);
+
+/* Per-device tuning used by later persistent traces on `device` (the library
+ * keeps one per device; rt_get_tuning reads it back).  RT_E_INVALID_ARG for
+ * values out of range. */
+rt_status rt_set_tuning(int device, const rt_tuning* t);
+rt_status rt_get_tuning(int device, rt_tuning* t);
+
+/* Autotuner: times every candidate tuning (refill_min_idle in {64, 32, 16, 8,
+ * 1} x blocks_per_cu in {1 .. the most that fit} x xcd_bands in {8, 1}) on a
+ * sample of the call - the same models and image, at most `max_freqs`
+ * frequencies spread over freq_hz - and installs the fastest as the device's
+ * tuning.  Each candidate's maps are compared with the first candidate's and
+ * must be bitwise identical (RT_E_INTERNAL otherwise).  best (HOST, may be
+ * NULL) receives the chosen tuning, best_ms and default_ms (HOST, may be NULL)
+ * the sample's time with it and with the defaults.  Synchronises hip_stream;
+ * allocates its own device buffers for the sample's maps. */
+rt_status rt_autotune(const rt_model* const* models, int32_t n_models, const double* freq_hz, int32_t n_freq,
+                      const rt_image_desc* image, const rt_params* params, int32_t max_freqs, rt_tuning* best,
+                      double* best_ms, double* default_ms, void* hip_stream);
+
 /* Trace maps for every (model, frequency) pair.
  *  models[n_models]: all on the current device, sharing one grid kind.
  *  freq_hz[n_freq]: HOST array, each > 0.

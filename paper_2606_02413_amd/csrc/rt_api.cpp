@@ -73,9 +73,10 @@ struct DeviceScratch {
   size_t start_cap = 0;          // pixels
   float* start_ne = nullptr;     // per-(model, pixel) n_e at the start point
   size_t start_ne_cap = 0;
-  void* adj_ws = nullptr;        // adjoint workspace (checkpoints, step buffer, channel adjoints), grown on demand
+  void* adj_ws = nullptr;        // adjoint workspace (checkpoints, chunk records, channel adjoints), grown on demand
   size_t adj_bytes = 0;
   int n_cu = 0;
+  rt_tuning tune{RT_ABI_VERSION, 64, 0, kXcds};  // launch tuning of the persistent trace
 };
 constexpr long long kAdjMaxCheckpoints = 128;  // per ray; longer rays thin their checkpoints
 constexpr long long kAdjCheckpointBudget = 8ll << 30;  // bytes of per-ray checkpoints per batch of tiles
@@ -508,22 +509,27 @@ rt_status rt_trace_maps(const rt_model* const* models, int32_t n_models, const d
           if (st != RT_OK) return st;
         }
     } else {
-      a.counters = next_counters(sc);
-      a.refill_min_idle = 64;
-      if (const char* e = std::getenv("RT_REFILL_MIN_IDLE")) {
-        const int v = std::atoi(e);
-        if (v >= 1 && v <= 64) a.refill_min_idle = v;
+      rt_tuning tune;
+      {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        tune = sc->tune;
       }
-      a.n_bands = kXcds;
+      a.counters = next_counters(sc);
+      a.refill_min_idle = tune.refill_min_idle;
+      const int bands = tune.xcd_bands;
+      a.n_bands = bands;
       const int n_images = n_models * n_freq;
       a.range_lo[0] = 0;
       for (int x = 0; x < kXcds; ++x) {
-        const int row0 = (x * a.tiles_v) / kXcds, row1 = ((x + 1) * a.tiles_v) / kXcds;
+        // rows of band x (bands = 1: every row in band 0, the others empty)
+        const int row0 = x < bands ? (x * a.tiles_v) / bands : a.tiles_v;
+        const int row1 = x < bands ? ((x + 1) * a.tiles_v) / bands : a.tiles_v;
         a.range_lo[x + 1] = a.range_lo[x] + (row1 - row0) * a.tiles_u * n_images;
       }
       st = hip_check(launch_fill_u32(a.counters, 0u, kXcds, s), "counter fill");
       if (st != RT_OK) return st;
-      const int per_cu = persistent_blocks_per_cu(mixed, a.g.kind);
+      int per_cu = persistent_blocks_per_cu(mixed, a.g.kind);
+      if (tune.blocks_per_cu > 0 && tune.blocks_per_cu < per_cu) per_cu = tune.blocks_per_cu;
       long long blocks = (long long)sc->n_cu * per_cu;
       const long long max_useful = ((long long)a.range_lo[kXcds] + 3) / 4;
       if (blocks > max_useful) blocks = max_useful;
@@ -531,6 +537,162 @@ rt_status rt_trace_maps(const rt_model* const* models, int32_t n_models, const d
       st = hip_check(launch_trace(a, false, mixed, int(blocks), s), "persistent trace launch");
       if (st != RT_OK) return st;
     }
+    return RT_OK;
+  } catch (...) {
+    return fail(RT_E_INTERNAL, "unexpected exception");
+  }
+}
+
+void rt_tuning_default(rt_tuning* t) {
+  if (!t) return;
+  t->abi_version = RT_ABI_VERSION;
+  t->refill_min_idle = 64;
+  t->blocks_per_cu = 0;
+  t->xcd_bands = kXcds;
+}
+
+rt_status rt_set_tuning(int device, const rt_tuning* t) {
+  try {
+    if (!t) return fail(RT_E_INVALID_ARG, "tuning is NULL");
+    if (t->abi_version != RT_ABI_VERSION) return fail(RT_E_INVALID_ARG, "tuning->abi_version mismatch");
+    if (t->refill_min_idle < 1 || t->refill_min_idle > 64) return fail(RT_E_INVALID_ARG, "refill_min_idle must be 1..64");
+    if (t->blocks_per_cu < 0 || t->blocks_per_cu > 8) return fail(RT_E_INVALID_ARG, "blocks_per_cu must be 0..8");
+    if (t->xcd_bands != 1 && t->xcd_bands != kXcds) return fail(RT_E_INVALID_ARG, "xcd_bands must be 1 or 8");
+    DeviceScratch* sc = nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    rt_status st = scratch_for(device, &sc);
+    if (st != RT_OK) return st;
+    sc->tune = *t;
+    return RT_OK;
+  } catch (...) {
+    return fail(RT_E_INTERNAL, "unexpected exception");
+  }
+}
+
+rt_status rt_get_tuning(int device, rt_tuning* t) {
+  try {
+    if (!t) return fail(RT_E_INVALID_ARG, "tuning is NULL");
+    DeviceScratch* sc = nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    rt_status st = scratch_for(device, &sc);
+    if (st != RT_OK) return st;
+    *t = sc->tune;
+    return RT_OK;
+  } catch (...) {
+    return fail(RT_E_INTERNAL, "unexpected exception");
+  }
+}
+
+rt_status rt_autotune(const rt_model* const* models, int32_t n_models, const double* freq_hz, int32_t n_freq,
+                      const rt_image_desc* image, const rt_params* params, int32_t max_freqs, rt_tuning* best,
+                      double* best_ms, double* default_ms, void* hip_stream) {
+  try {
+    if (max_freqs < 1) return fail(RT_E_INVALID_ARG, "max_freqs must be >= 1");
+    if (!models || n_models < 1 || !models[0]) return fail(RT_E_INVALID_ARG, "need at least one model");
+    if (!freq_hz || n_freq < 1) return fail(RT_E_INVALID_ARG, "need at least one frequency");
+    if (!image || !params) return fail(RT_E_INVALID_ARG, "image/params is NULL");
+    if (params->flags & RT_SCHED_PLAIN) return fail(RT_E_INVALID_ARG, "the tuning applies to the persistent trace");
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    const int dev = models[0]->device;
+    rt_status st = hip_check(hipSetDevice(dev), "hipSetDevice");
+    if (st != RT_OK) return st;
+    DeviceScratch* sc = nullptr;
+    rt_tuning saved;
+    {
+      std::lock_guard<std::mutex> lk(g_scratch_mu);
+      st = scratch_for(dev, &sc);
+      if (st != RT_OK) return st;
+      saved = sc->tune;
+    }
+    // the sample: at most max_freqs frequencies spread over the list
+    const int m = std::min<int>(max_freqs, n_freq);
+    std::vector<double> fs(m);
+    for (int k = 0; k < m; ++k) fs[k] = freq_hz[int(((long long)(2 * k + 1) * n_freq) / (2 * m))];
+    const long long n_out = (long long)n_models * m * image->nu * image->nv;
+    if (n_out < 1 || n_out > (1ll << 31) - 1) return fail(RT_E_CAPACITY, "sample too large");
+    float* ref = nullptr;
+    float* cur = nullptr;
+    unsigned* diff = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    auto cleanup = [&]() {
+      if (e0) (void)hipEventDestroy(e0);
+      if (e1) (void)hipEventDestroy(e1);
+      dev_free(ref, size_t(n_out) * sizeof(float));
+      dev_free(cur, size_t(n_out) * sizeof(float));
+      dev_free(diff, sizeof(unsigned));
+      std::lock_guard<std::mutex> lk(g_scratch_mu);
+      sc->tune = saved;
+    };
+    st = dev_alloc((void**)&ref, size_t(n_out) * sizeof(float), "autotune maps");
+    if (st == RT_OK) st = dev_alloc((void**)&cur, size_t(n_out) * sizeof(float), "autotune maps");
+    if (st == RT_OK) st = dev_alloc((void**)&diff, sizeof(unsigned), "autotune counter");
+    if (st == RT_OK) st = hip_check(hipEventCreate(&e0), "event");
+    if (st == RT_OK) st = hip_check(hipEventCreate(&e1), "event");
+    if (st != RT_OK) { cleanup(); return st; }
+    const bool mixed = (params->flags & RT_PREC_ALL_FP32) == 0;
+    const int max_per_cu = persistent_blocks_per_cu(mixed, models[0]->geom.kind);
+    std::vector<rt_tuning> cand;
+    rt_tuning d;
+    rt_tuning_default(&d);
+    cand.push_back(d);  // the defaults first: the reference maps
+    const int refills[5] = {64, 32, 16, 8, 1};
+    for (int bands : {int(kXcds), 1})
+      for (int bpc = 1; bpc <= max_per_cu; ++bpc)
+        for (int rf : refills) {
+          rt_tuning t = d;
+          t.refill_min_idle = rf;
+          t.blocks_per_cu = bpc;
+          t.xcd_bands = bands;
+          if (!(bands == d.xcd_bands && rf == d.refill_min_idle && bpc == max_per_cu)) cand.push_back(t);
+        }
+    auto run = [&](const rt_tuning& t, float* out, double* ms) -> rt_status {
+      {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        sc->tune = t;
+      }
+      rt_status r = hip_check(hipEventRecord(e0, s), "event record");
+      if (r == RT_OK)
+        r = rt_trace_maps(models, n_models, fs.data(), m, image, params, out, nullptr, nullptr, nullptr, 0, 0,
+                          nullptr, nullptr, hip_stream);
+      if (r == RT_OK) r = hip_check(hipEventRecord(e1, s), "event record");
+      if (r == RT_OK) r = hip_check(hipEventSynchronize(e1), "event sync");
+      float f = 0.f;
+      if (r == RT_OK) r = hip_check(hipEventElapsedTime(&f, e0, e1), "event time");
+      *ms = double(f);
+      return r;
+    };
+    double ms = 0.0;
+    st = run(cand[0], ref, &ms);  // warm-up (first use of the model and the launch table)
+    if (st == RT_OK) st = run(cand[0], ref, &ms);
+    const double ms_default = ms;
+    rt_tuning chosen = cand[0];
+    double ms_best = ms;
+    for (size_t k = 1; st == RT_OK && k < cand.size(); ++k) {
+      st = run(cand[k], cur, &ms);
+      if (st != RT_OK) break;
+      unsigned nd = 0;
+      st = hip_check(launch_fill_u32(diff, 0u, 1, s), "diff fill");
+      if (st == RT_OK) st = hip_check(launch_count_diff(reinterpret_cast<const unsigned*>(ref),
+                                                        reinterpret_cast<const unsigned*>(cur), n_out, diff, s),
+                                      "map compare");
+      if (st == RT_OK) st = hip_check(hipMemcpyAsync(&nd, diff, sizeof(unsigned), hipMemcpyDeviceToHost, s), "copy");
+      if (st == RT_OK) st = hip_check(hipStreamSynchronize(s), "stream sync");
+      if (st != RT_OK) break;
+      if (nd != 0) {
+        cleanup();
+        return fail(RT_E_INTERNAL, "autotune: maps differ between launch tunings");
+      }
+      if (ms < ms_best) { ms_best = ms; chosen = cand[k]; }
+    }
+    cleanup();
+    if (st != RT_OK) return st;
+    {
+      std::lock_guard<std::mutex> lk(g_scratch_mu);
+      sc->tune = chosen;
+    }
+    if (best) *best = chosen;
+    if (best_ms) *best_ms = ms_best;
+    if (default_ms) *default_ms = ms_default;
     return RT_OK;
   } catch (...) {
     return fail(RT_E_INTERNAL, "unexpected exception");

@@ -322,6 +322,19 @@ hipError_t launch_start_index(const TraceArgs& a, double* out, float* ne_out, hi
   return hipGetLastError();
 }
 
+// Number of 32-bit words that differ between a and b (added to *count).
+__global__ void k_count_diff(const unsigned* a, const unsigned* b, long long n, unsigned* count) {
+  unsigned c = 0;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    c += (a[i] != b[i]) ? 1u : 0u;
+  if (c) atomicAdd(count, c);
+}
+
+hipError_t launch_count_diff(const unsigned* a, const unsigned* b, long long n, unsigned* count, hipStream_t s) {
+  hipLaunchKernelGGL(k_count_diff, dim3(grid_for(n, 256)), dim3(256), 0, s, a, b, n, count);
+  return hipGetLastError();
+}
+
 hipError_t launch_fill_u32(unsigned* p, unsigned val, long long n, hipStream_t s) {
   hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(n, 256)), dim3(256), 0, s, p, val, n);
   return hipGetLastError();

@@ -57,6 +57,15 @@ class Params(C.Structure):
 
 INFO_DTYPE = np.dtype([("n_steps", "<i4"), ("code", "i1"), ("flags", "i1"), ("_pad", "i1", (2,)),
                        ("exit_pos", "<f4", (3,)), ("tau", "<f4"), ("ln_s_end", "<f4"), ("r_min", "<f4")])
+class Tuning(C.Structure):
+    _fields_ = [("abi_version", C.c_uint32), ("refill_min_idle", C.c_int32), ("blocks_per_cu", C.c_int32),
+                ("xcd_bands", C.c_int32)]
+
+    def as_dict(self):
+        return {"refill_min_idle": int(self.refill_min_idle), "blocks_per_cu": int(self.blocks_per_cu),
+                "xcd_bands": int(self.xcd_bands)}
+
+
 STATS_DTYPE = np.dtype([("ray_steps", "<u8"), ("max_steps", "<u4"), ("code_count", "<u4", (6,)), ("_pad", "<u4")])
 assert INFO_DTYPE.itemsize == 32 and STATS_DTYPE.itemsize == 40
 
@@ -92,6 +101,16 @@ def lib():
         L.rt_abi_version.restype = C.c_uint32
         L.rt_params_default.argtypes = [C.POINTER(Params)]
         L.rt_params_default.restype = None
+        L.rt_tuning_default.argtypes = [C.POINTER(Tuning)]
+        L.rt_tuning_default.restype = None
+        L.rt_set_tuning.argtypes = [C.c_int, C.POINTER(Tuning)]
+        L.rt_set_tuning.restype = C.c_int
+        L.rt_get_tuning.argtypes = [C.c_int, C.POINTER(Tuning)]
+        L.rt_get_tuning.restype = C.c_int
+        L.rt_autotune.argtypes = [C.POINTER(vp), C.c_int32, C.POINTER(C.c_double), C.c_int32, C.POINTER(ImageDesc),
+                                  C.POINTER(Params), C.c_int32, C.POINTER(Tuning), C.POINTER(C.c_double),
+                                  C.POINTER(C.c_double), vp]
+        L.rt_autotune.restype = C.c_int
         _lib = L
     return _lib
 
@@ -229,6 +248,76 @@ def trace_maps(models, freqs, image, prm, *, info=True, stats=True, path_rays=No
                                int(path_capacity), ptr("path") if n_path else C.c_void_p(0),
                                ptr("path_len") if n_path else C.c_void_p(0), _stream_ptr(stream)))
     return res
+
+
+def tuning(refill_min_idle=64, blocks_per_cu=0, xcd_bands=8):
+    t = Tuning()
+    lib().rt_tuning_default(C.byref(t))
+    t.refill_min_idle, t.blocks_per_cu, t.xcd_bands = int(refill_min_idle), int(blocks_per_cu), int(xcd_bands)
+    return t
+
+
+def set_tuning(t, device=0):
+    """Install a launch tuning of the persistent trace on `device` (a Tuning or a dict)."""
+    if isinstance(t, dict):
+        t = tuning(**t)
+    _check(lib().rt_set_tuning(int(device), C.byref(t)))
+
+
+def get_tuning(device=0):
+    t = Tuning()
+    _check(lib().rt_get_tuning(int(device), C.byref(t)))
+    return t
+
+
+def tuning_key(models, freqs, image, prm, max_freqs):
+    """Cache key of a tuning: the device, grid, image, batch shape and stepping
+    controls it was measured on (the frequencies by count and range)."""
+    import torch
+    if isinstance(models, Model):
+        models = [models]
+    freqs = np.atleast_1d(np.asarray(freqs, dtype=np.float64))
+    d = models[0].desc
+    parts = [torch.cuda.get_device_name(models[0].device), f"kind{d.kind}", f"{d.n0}x{d.n1}x{d.n2}",
+             f"r{d.r_in:g}-{d.r_max:g}", f"img{image.nu}x{image.nv}", f"hw{image.half_u:g}x{image.half_v:g}",
+             f"models{len(models)}", f"freqs{freqs.size}:{freqs.min():.6g}-{freqs.max():.6g}",
+             f"flags{prm.flags}", f"ds{prm.ds_max:g}", f"nf{prm.n_floor:g}", f"sample{int(max_freqs)}"]
+    return "|".join(parts)
+
+
+def autotune(models, freqs, image, prm, *, max_freqs=8, cache=None, stream=None):
+    """Pick the launch tuning of the persistent trace for this workload and install it.
+
+    Runs rt_autotune (every candidate on a sample of at most max_freqs
+    frequencies, maps checked bitwise against the defaults) unless `cache` (a
+    JSON file path) already holds a tuning for the same key; stores new results
+    there.  Returns a dict: tuning, key, best_ms, default_ms, cached."""
+    import json
+    if isinstance(models, Model):
+        models = [models]
+    key = tuning_key(models, freqs, image, prm, max_freqs)
+    table = {}
+    if cache is not None and os.path.exists(cache):
+        with open(cache) as fh:
+            table = json.load(fh)
+    if key in table:
+        set_tuning(table[key]["tuning"], models[0].device)
+        return dict(table[key], key=key, cached=True)
+    freqs = np.ascontiguousarray(np.atleast_1d(freqs), dtype=np.float64)
+    handles = (C.c_void_p * len(models))(*[m.handle.value for m in models])
+    best = Tuning()
+    best_ms, default_ms = C.c_double(0.0), C.c_double(0.0)
+    _check(lib().rt_autotune(handles, len(models), freqs.ctypes.data_as(C.POINTER(C.c_double)), freqs.shape[0],
+                             C.byref(image), C.byref(prm), int(max_freqs), C.byref(best), C.byref(best_ms),
+                             C.byref(default_ms), _stream_ptr(stream)))
+    rec = {"tuning": best.as_dict(), "best_ms": best_ms.value, "default_ms": default_ms.value}
+    if cache is not None:
+        table[key] = rec
+        tmp = cache + ".tmp"
+        with open(tmp, "w") as fh:
+            json.dump(table, fh, indent=1, sort_keys=True)
+        os.replace(tmp, cache)
+    return dict(rec, key=key, cached=False)
 
 
 def capture_trace_maps(models, freqs, image, prm, *, info=False, stats=True):

@@ -94,6 +94,31 @@ def test_trace_argument_validation(R):
     assert st in (1, 5)
 
 
+def test_tuning_defaults_and_validation(R):
+    """Launch tuning: defaults, and values out of range rejected before any
+    device work; the autotuner rejects bad arguments the same way."""
+    L = R.lib()
+    t = R.Tuning()
+    L.rt_tuning_default(C.byref(t))
+    assert t.as_dict() == {"refill_min_idle": 64, "blocks_per_cu": 0, "xcd_bands": 8} and t.abi_version == 1
+    for kw in (dict(refill_min_idle=0), dict(refill_min_idle=65), dict(blocks_per_cu=-1), dict(blocks_per_cu=9),
+               dict(xcd_bands=2), dict(xcd_bands=0)):
+        bad = R.tuning(**kw)
+        assert L.rt_set_tuning(0, C.byref(bad)) == 1, kw
+    bad = R.tuning()
+    bad.abi_version = 7
+    assert L.rt_set_tuning(0, C.byref(bad)) == 1
+    assert L.rt_set_tuning(0, None) == 1 and L.rt_get_tuning(0, None) == 1
+    im = R.image_desc(8, 2.0)
+    f = (C.c_double * 1)(150e6)
+    p = R.params()
+    assert L.rt_autotune(None, 1, f, 1, C.byref(im), C.byref(p), 4, None, None, None, None) == 1
+    assert L.rt_autotune(None, 1, f, 1, C.byref(im), C.byref(p), 0, None, None, None, None) == 1
+    plain = R.params(plain=True)
+    h = (C.c_void_p * 1)(1)
+    assert L.rt_autotune(h, 1, f, 1, C.byref(im), C.byref(plain), 4, None, None, None, None) == 1
+
+
 def test_binding_fails_loudly_without_library(R, monkeypatch):
     monkeypatch.setattr(R, "_lib", None)
     monkeypatch.setattr(R, "LIB_PATH", "/nonexistent/librtsun.so")

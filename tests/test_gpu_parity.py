@@ -69,6 +69,50 @@ def test_persistent_equals_plain_bitwise(R, structured_small):
     assert a["stats"]["ray_steps"] == b["stats"]["ray_steps"]
 
 
+def test_every_launch_tuning_gives_the_same_maps(R, structured_small):
+    """Every tuning the autotuner may choose (refill threshold, blocks per CU,
+    die bands) traces the same bits as the plain per-image launch."""
+    cor, m = structured_small
+    kw = PU.step_kwargs(0.01, 0.1)
+    freqs = corona.log_freqs(3)
+    print("case launch tunings", flush=True)
+    ref = PU.gpu_trace([m], freqs, 45, 3.0, kw, plain=True)
+    try:
+        for rf, bpc, bands in ((1, 1, 1), (8, 2, 8), (32, 1, 8), (16, 0, 1)):
+            R.set_tuning(R.tuning(rf, bpc, bands), m.device)
+            got = PU.gpu_trace([m], freqs, 45, 3.0, kw, plain=False)
+            assert np.array_equal(ref["tb"].view(np.uint32), got["tb"].view(np.uint32)), (rf, bpc, bands)
+            assert np.array_equal(ref["info"].view(np.uint8), got["info"].view(np.uint8)), (rf, bpc, bands)
+    finally:
+        R.set_tuning(R.tuning(), m.device)
+
+
+def test_autotune_installs_a_tuning_and_caches_it(R, structured_small, tmp_path):
+    import torch
+    cor, m = structured_small
+    freqs = corona.log_freqs(4)
+    im = R.image_desc(45, 3.0)
+    prm = R.params(ds_max=0.01, n_floor=0.1)
+    cache = str(tmp_path / "tuning.json")
+    print("case autotune", flush=True)
+    try:
+        res = R.autotune([m], freqs, im, prm, max_freqs=2, cache=cache)
+        assert not res["cached"] and res["best_ms"] > 0 and res["best_ms"] <= res["default_ms"]
+        t = res["tuning"]
+        assert 1 <= t["refill_min_idle"] <= 64 and t["xcd_bands"] in (1, 8) and t["blocks_per_cu"] >= 0
+        assert R.get_tuning(m.device).as_dict() == t
+        R.set_tuning(R.tuning(), m.device)
+        again = R.autotune([m], freqs, im, prm, max_freqs=2, cache=cache)
+        assert again["cached"] and again["tuning"] == t and R.get_tuning(m.device).as_dict() == t
+        tuned = R.trace_maps([m], freqs, im, prm, info=False, stats=False)["tb"]
+        plain = R.trace_maps([m], freqs, im, R.params(ds_max=0.01, n_floor=0.1, plain=True), info=False,
+                             stats=False)["tb"]
+        torch.cuda.synchronize()
+        assert torch.equal(tuned, plain)
+    finally:
+        R.set_tuning(R.tuning(), m.device)
+
+
 @pytest.mark.parametrize("adaptive", [False, True])
 def test_structured_ragged_image(R, orc, structured_small, adaptive):
     """Random-field corona with active regions, r 1-30, ragged 37x29 image (tiles with a tail)."""
