@@ -243,7 +243,8 @@ rt_status rt_trace_maps(const rt_model* const* models, int32_t n_models, const d
  * values its adjoint needs (188 bytes a step), and then sweeps the chunk
  * backward from that record.  The image tiles (8 x 8 pixels of one frequency)
  * are traced and swept in batches whose checkpoints (up to 10 KB a ray) fit an
- * 8 GiB budget.  Channel adjoints are accumulated per lane and cell in FP32 and
+ * 8 GiB budget (the environment variable RT_ADJOINT_CHECKPOINT_BYTES, read at
+ * each call, sets another; at least one tile is taken per batch).  Channel adjoints are accumulated per lane and cell in FP32 and
  * added into an FP64 per-vertex accumulator with atomics, so the last bits can
  * vary between runs.  Mixed precision only: RT_PREC_ALL_FP32,
  * RT_DETERMINISTIC_GRAD and RT_TEST_NO_ABSORPTION return RT_E_UNSUPPORTED.  The

@@ -1,5 +1,6 @@
-// Kernels of the reverse mode: the per-ray adjoint launch and the gather that
-// turns channel adjoints into d loss / d ln n_e and d loss / d ln T per vertex.
+// Kernels of the reverse mode: the forward pass with per-ray checkpoints, the
+// reverse sweeps, and the gather that turns channel adjoints into
+// d loss / d ln n_e and d loss / d ln T per vertex.
 #include <hip/hip_runtime.h>
 
 #include "rt_internal.hpp"

@@ -28,13 +28,15 @@ rt_status fail(rt_status s, const std::string& msg) {
 
 std::atomic<long long> g_device_bytes{0};
 
-long long byte_cap() {
-  const char* e = std::getenv("RT_MAX_DEVICE_BYTES");
+long long env_bytes(const char* name) {
+  const char* e = std::getenv(name);
   if (!e || !*e) return -1;
   char* end = nullptr;
   long long v = std::strtoll(e, &end, 10);
   return (end && *end == '\0' && v >= 0) ? v : -1;
 }
+
+long long byte_cap() { return env_bytes("RT_MAX_DEVICE_BYTES"); }
 
 // Allocation through one place so the optional byte cap applies everywhere.
 rt_status dev_alloc(void** p, size_t bytes, const char* what) {
@@ -730,7 +732,8 @@ rt_status rt_trace_adjoint(const rt_model* model, const double* freq_hz, int32_t
     // checkpoints are kept per ray: the tiles are traced and swept in batches
     // whose checkpoints fit the budget
     const long long tile_bytes = (long long)kWaveLanes * (cap * kCkptFields * (long long)sizeof(double) + 3 * 4);
-    long long batch = kAdjCheckpointBudget / tile_bytes;
+    const long long budget = env_bytes("RT_ADJOINT_CHECKPOINT_BYTES");
+    long long batch = (budget > 0 ? budget : kAdjCheckpointBudget) / tile_bytes;
     if (batch < 1) batch = 1;
     if (batch > n_tiles) batch = n_tiles;
     long long blocks = (long long)sc->n_cu * adjoint_blocks_per_cu(a.g.kind);

@@ -139,6 +139,26 @@ def test_checkpoint_interval_does_not_change_the_gradient(R, small):
     np.testing.assert_allclose(t2, t1, rtol=0, atol=1e-6 * np.abs(t1).max())
 
 
+def test_batches_of_tiles_give_the_same_gradient(R, small, monkeypatch):
+    """A checkpoint budget of two tiles splits the ragged 20 x 13 image at three
+    frequencies (18 tiles) into nine forward + sweep batches: same loss and maps,
+    same gradient up to the order of the atomic additions."""
+    cor, m = small
+    freqs = np.array([40e6, 120e6, 300e6])
+    im = R.image_desc(20, 2.0, nv=13, half_v=1.4)
+    prm = R.params(ds_max=0.01, n_floor=0.1)
+    w = _weights((3, 13, 20), 1003)
+    print("case adjoint batches", flush=True)
+    one = _run(R, m, freqs, im, prm, w)
+    tile_bytes = 64 * (128 * 10 * 8 + 12)  # 128 checkpoints of 80 B and a 12 B record per ray
+    monkeypatch.setenv("RT_ADJOINT_CHECKPOINT_BYTES", str(2 * tile_bytes))
+    many = _run(R, m, freqs, im, prm, w)
+    assert np.array_equal(one[3], many[3])
+    assert many[0] == pytest.approx(one[0], rel=1e-12)
+    for a, b in ((one[1], many[1]), (one[2], many[2])):
+        np.testing.assert_allclose(b, a, rtol=0, atol=1e-6 * np.abs(a).max())
+
+
 def test_gradient_matches_oracle_long_rays(R, orc):
     """64x32x64 model over 1-30 R_sun: ~6,000 steps per ray at 40 and 150 MHz."""
     cor = corona.structured(nr=64, nt=32, nph=64, r_in=1.0, r_max=30.0, seed=0, n_feat=256)
