@@ -69,6 +69,8 @@ def parse():
                     help="fixed launch tuning refill_min_idle,blocks_per_cu,xcd_bands instead of autotuning")
     ap.add_argument("--adjoint-only", action="store_true",
                     help="only run the adjoint / forward timing on the adjoint workload (for profiling)")
+    ap.add_argument("--modes", action="store_true",
+                    help="study: straight line of sight vs refraction, magnification on/off, on the structured model")
     ap.add_argument("--batching", action="store_true",
                     help="only run the batching study (batched vs plain on the 4-model 64-frequency workload)")
     ap.add_argument("--precision", action="store_true",
@@ -223,6 +225,64 @@ def precision_study(n_pixels=4096, seconds_note=True):
     model.close()
 
 
+def modes_study():
+    """Straight lines of sight vs refractive tracing, and the magnification term
+    on and off, on the structured workload's model (256x128x256, r 1-30 R_sun,
+    8 active regions, seed 0), 512^2 image over +/-3 R_sun, at 40, 60, 80, 150,
+    280, 550 and 800 MHz (Sec. 3.3 compares these maps; Sec. 3.4 the term).
+    Per frequency: the maximum T_b of each mode; the mean T_b on the disc centre
+    (projected radius < 0.5 R_sun) and in the limb annulus (0.9-1.1 R_sun), and
+    their ratio (limb brightening); the median and 99th percentile of
+    |T_b(LOS) - T_b(refraction)| / T_b(refraction) over pixels within 2 R_sun;
+    the same for the magnification term (refraction with vs without it); and
+    the largest |S_end / S_0 - 1| over rays (from ln S at the end of each ray).
+    Each mode's trace is timed.  Prints one JSON line."""
+    import torch
+    from paper_2606_02413_amd import corona, rtsun as R
+    wl = corona.workload("structured")
+    model = R.Model.from_corona(wl.models(device="cuda")[0])
+    n, hw = wl.n_pix, wl.half_width
+    im = R.image_desc(n, hw)
+    freqs = np.array([40e6, 60e6, 80e6, 150e6, 280e6, 550e6, 800e6])
+    c = (np.arange(n) + 0.5) * (2 * hw / n) - hw
+    rho = np.hypot(c[None, :], c[:, None])
+    centre, limb, inner = rho < 0.5, (rho > 0.9) & (rho < 1.1), rho < 2.0
+    modes = {"los": dict(refraction=False, magnification=False), "refraction": dict(magnification=False),
+             "full": dict()}
+    maps, lns, ms = {}, {}, {}
+    for name, kw in modes.items():
+        prm = R.params(ds_max=wl.ds_max, n_floor=wl.n_floor, max_steps=wl.max_steps, **kw)
+        out = R.trace_maps([model], freqs, im, prm, info=True, stats=False)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        R.trace_maps([model], freqs, im, prm, info=True, stats=False, out=out)
+        e1.record()
+        torch.cuda.synchronize()
+        ms[name] = e0.elapsed_time(e1)
+        maps[name] = out["tb"][0].double().cpu().numpy()
+        lns[name] = R.decode_info(out["info"][0])["ln_s_end"].astype(np.float64)
+        progress(f"modes: {name} {ms[name]:.0f} ms")
+    rows = []
+    for k, f in enumerate(freqs):
+        row = {"MHz": round(f / 1e6, 1)}
+        for name in modes:
+            t = maps[name][k]
+            row[f"max_tb_{name}"] = float(t.max())
+            row[f"limb_over_centre_{name}"] = float(t[limb].mean() / t[centre].mean())
+        ref = maps["refraction"][k]
+        for a, b, tag in (("los", "refraction", "los_vs_refraction"), ("full", "refraction", "magnification")):
+            d = np.abs(maps[a][k] - maps[b][k])[inner] / np.maximum(ref[inner], 1.0)
+            row[f"{tag}_median"] = float(np.median(d))
+            row[f"{tag}_p99"] = float(np.quantile(d, 0.99))
+        row["max_abs_S_end_over_S0_minus_1"] = float(np.abs(np.expm1(lns["full"][k])).max())
+        rows.append(row)
+    print(json.dumps({"study": "modes", "workload": "structured model, 512^2 over +/-3 R_sun", "ms": ms,
+                      "per_frequency": rows}), flush=True)
+    model.close()
+
+
 def batching_study():
     """Batched (one persistent launch over every model, frequency and tile) vs
     plain (one launch per image) on (a) the batched workload: the structured
@@ -311,6 +371,9 @@ def main():
         return
     if args.batching:
         batching_study()
+        return
+    if args.modes:
+        modes_study()
         return
     if args.adjoint_only:
         import torch
