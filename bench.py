@@ -69,6 +69,8 @@ def parse():
                     help="fixed launch tuning refill_min_idle,blocks_per_cu,xcd_bands instead of autotuning")
     ap.add_argument("--adjoint-only", action="store_true",
                     help="only run the adjoint / forward timing on the adjoint workload (for profiling)")
+    ap.add_argument("--fit", type=int, default=0, metavar="ITERS",
+                    help="study: recover a structured corona's ln n_e, ln T from its own maps (ITERS Adam steps)")
     ap.add_argument("--modes", action="store_true",
                     help="study: straight line of sight vs refraction, magnification on/off, on the structured model")
     ap.add_argument("--batching", action="store_true",
@@ -283,6 +285,59 @@ def modes_study():
     model.close()
 
 
+def fit_study(iters):
+    """Coronal fitting through the adjoint: the maps of a structured corona
+    (128x64x128, r 1-30 R_sun, random field and 8 active regions, seed 0) at the
+    8 structured-workload frequencies on a 128^2 image over +/-3 R_sun are the
+    data; the fit starts from the same corona without its random field and
+    takes `iters` Adam steps (lr 0.01) on (ln n_e, ln T) of every vertex, the
+    loss being the mean squared T_b error over the mean squared data.  Reports
+    the loss and the RMS error of ln n_e on the vertices the rays reach, per
+    step, and the time of a forward + backward pass."""
+    import torch
+    from paper_2606_02413_amd import corona, rtsun as R
+    kw = dict(nr=128, nt=64, nph=128, r_in=1.0, r_max=30.0, seed=0, n_feat=256)
+    truth = corona.structured(**kw)
+    start = corona.structured(amp=0.0, **kw)
+    wl = corona.workload("structured")
+    model = R.Model.from_corona(truth)
+    im = R.image_desc(128, 3.0)
+    prm = R.params(ds_max=wl.ds_max, n_floor=wl.n_floor, max_steps=wl.max_steps)
+    F = R.rtsun_function()
+    ln_ne_true = torch.log(torch.from_numpy(truth.ne).double()).cuda()
+    ln_te_true = torch.log(torch.from_numpy(truth.te).double()).cuda()
+    with torch.no_grad():
+        data = F.apply(ln_ne_true.float(), ln_te_true.float(), model, wl.freqs, im, prm).clone()
+    norm = float((data.double() ** 2).mean())
+    ln_ne = torch.log(torch.from_numpy(start.ne)).cuda().requires_grad_(True)
+    ln_te = torch.log(torch.from_numpy(start.te)).cuda().requires_grad_(True)
+    opt = torch.optim.Adam([ln_ne, ln_te], lr=0.01)
+    hist = []
+    reach = None
+    times = []
+    for it in range(iters + 1):
+        opt.zero_grad()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        tb = F.apply(ln_ne, ln_te, model, wl.freqs, im, prm)
+        loss = ((tb - data) ** 2).mean() / norm
+        loss.backward()
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        if reach is None:
+            reach = ln_ne.grad != 0
+        err = float(torch.sqrt(((ln_ne.detach().double() - ln_ne_true)[reach] ** 2).mean()))
+        hist.append({"step": it, "loss": float(loss), "rms_ln_ne_error_reached": err})
+        if it % 5 == 0:
+            progress(f"fit step {it}: loss {float(loss):.4e} rms ln n_e error {err:.4f}")
+        if it < iters:
+            opt.step()
+    print(json.dumps({"study": "fit", "grid": "128x64x128", "image": "128^2 over +/-3 R_sun x 8 freq",
+                      "vertices_reached": int(reach.sum()), "forward_backward_s_median": float(np.median(times[1:])),
+                      "history": hist}), flush=True)
+    model.close()
+
+
 def batching_study():
     """Batched (one persistent launch over every model, frequency and tile) vs
     plain (one launch per image) on (a) the batched workload: the structured
@@ -374,6 +429,9 @@ def main():
         return
     if args.modes:
         modes_study()
+        return
+    if args.fit > 0:
+        fit_study(args.fit)
         return
     if args.adjoint_only:
         import torch

@@ -324,6 +324,36 @@ def test_autograd_function_backward_is_the_adjoint(R):
     np.testing.assert_array_equal(tb.detach().cpu().numpy(), ref["tb"].cpu().numpy())
     m.close()
 
+def test_fitting_steps_reduce_the_misfit(R):
+    """Three Adam steps on (ln n_e, ln T) through the autograd Function, from
+    the structured corona without its random field towards the maps of the full
+    one, lower the mean squared relative T_b error at every step."""
+    import torch
+    kw = dict(nr=32, nt=16, nph=32, r_in=1.0, r_max=5.0, seed=3, n_feat=128)
+    truth, start = corona.structured(**kw), corona.structured(amp=0.0, **kw)
+    m = R.Model.from_corona(truth)
+    freqs, im, prm = [80e6, 200e6], R.image_desc(16, 2.0), R.params(ds_max=0.01, n_floor=0.1)
+    F = R.rtsun_function()
+    print("case fitting steps", flush=True)
+    with torch.no_grad():
+        data = F.apply(torch.log(torch.from_numpy(truth.ne)).cuda(), torch.log(torch.from_numpy(truth.te)).cuda(),
+                       m, freqs, im, prm).clone()
+    scale = torch.clamp(data, min=1.0e3)
+    ln_ne = torch.log(torch.from_numpy(start.ne)).cuda().requires_grad_(True)
+    ln_te = torch.log(torch.from_numpy(start.te)).cuda().requires_grad_(True)
+    opt = torch.optim.Adam([ln_ne, ln_te], lr=0.01)
+    losses = []
+    for _ in range(4):
+        opt.zero_grad()
+        loss = (((F.apply(ln_ne, ln_te, m, freqs, im, prm) - data) / scale) ** 2).mean()
+        loss.backward()
+        losses.append(float(loss))
+        opt.step()
+    print("fit losses", losses, flush=True)
+    assert all(b < a for a, b in zip(losses, losses[1:])), losses
+    m.close()
+
+
 
 def test_gradient_agrees_with_central_differences(R, orc, small):
     """The GPU gradient against central finite differences of the FP64 loss
