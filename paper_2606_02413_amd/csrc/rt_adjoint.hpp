@@ -43,14 +43,24 @@ struct GradAcc {
 constexpr int kLogWords = 4 + kGradChannels;  // key, u, v, w, channel adjoints
 constexpr int kLogEntries = 7;                // evaluations logged before a replay
 
-// Write entry e: word j at lg[(kLogWords e + j) * kWaveLanes].
-__device__ __forceinline__ void log_entry(float* lg, int e, const Loc& L, float c0, float c1, float c2, float c3,
-                                          float c4) {
+// Entry e, word j at lg[(kLogWords e + j) * kWaveLanes]: key, u, v, w, then
+// the adjoints of the channels (n_e, three index gradients, T).  A gradient
+// entry writes the three gradient channels (and n_e when it has one), a value
+// entry n_e and T; the replay reads only those.
+__device__ __forceinline__ void log_grad_entry(float* lg, int e, const Loc& L, bool with_n, float c0, float c1,
+                                               float c2, float c3) {
   float* p = lg + e * kLogWords * kWaveLanes;
   p[0] = __int_as_float(L.key);
   p[kWaveLanes] = L.u; p[2 * kWaveLanes] = L.v; p[3 * kWaveLanes] = L.w;
-  p[4 * kWaveLanes] = c0; p[5 * kWaveLanes] = c1; p[6 * kWaveLanes] = c2;
-  p[7 * kWaveLanes] = c3; p[8 * kWaveLanes] = c4;
+  if (with_n) p[4 * kWaveLanes] = c0;
+  p[5 * kWaveLanes] = c1; p[6 * kWaveLanes] = c2; p[7 * kWaveLanes] = c3;
+}
+
+__device__ __forceinline__ void log_value_entry(float* lg, int e, const Loc& L, float c0, float c4) {
+  float* p = lg + e * kLogWords * kWaveLanes;
+  p[0] = __int_as_float(L.key);
+  p[kWaveLanes] = L.u; p[2 * kWaveLanes] = L.v; p[3 * kWaveLanes] = L.w;
+  p[4 * kWaveLanes] = c0; p[8 * kWaveLanes] = c4;
 }
 
 // Move the lane's LDS accumulator to cell `key` (-1: empty it).  Corners shared
@@ -113,12 +123,42 @@ __device__ __forceinline__ void acc_add(GradAcc& A, const float s[8][kGradChanne
     for (int ch = 0; ch < kGradChannels; ++ch) A.v[(k * kGradChannels + ch) * kWaveLanes] += s[k][ch];
 }
 
-// Replay log entries [0, n).  Entries of the accumulator's cell are summed in
-// registers (sa), entries of one other cell too (sb); after the loop sa is added
-// to the accumulator and a lane that met another cell moves its accumulator
-// there.  The moves (and their atomics) of all lanes thus happen at one point
-// of the program rather than wherever each lane meets a new cell; a third
-// cell within one replay takes the same move early.
+// Corner sums of one log entry added to s: a value entry (VALUE) carries n_e
+// and T, a gradient entry the three gradient channels and n_e when WITH_N.
+__device__ __forceinline__ void entry_add(float s[8][kGradChannels], const float* p, const float W[8], bool value,
+                                          bool with_n) {
+  if (value) {
+    const float c0 = p[4 * kWaveLanes], c4 = p[8 * kWaveLanes];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      s[k][0] = fmaf(W[k], c0, s[k][0]);
+      s[k][4] = fmaf(W[k], c4, s[k][4]);
+    }
+  } else {
+    const float c1 = p[5 * kWaveLanes], c2 = p[6 * kWaveLanes], c3 = p[7 * kWaveLanes];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      s[k][1] = fmaf(W[k], c1, s[k][1]);
+      s[k][2] = fmaf(W[k], c2, s[k][2]);
+      s[k][3] = fmaf(W[k], c3, s[k][3]);
+    }
+    if (with_n) {
+      const float c0 = p[4 * kWaveLanes];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) s[k][0] = fmaf(W[k], c0, s[k][0]);
+    }
+  }
+}
+
+// Replay log entries [0, n): entry 0 is a value entry when VALUE0, the others
+// gradient entries, the last one with an n_e channel when N_LAST.  Entries of
+// the accumulator's cell are summed in registers (sa), entries of one other
+// cell too (sb); after the loop sa is added to the accumulator and a lane that
+// met another cell moves its accumulator there.  The moves (and their atomics)
+// of all lanes thus happen at one point of the program rather than wherever
+// each lane meets a new cell; a third cell within one replay takes the same
+// move early.
+template <bool VALUE0, bool N_LAST>
 __device__ __forceinline__ void log_replay(const DevGeom& g, GradAcc& A, double* gacc, const float* lg, int n) {
   float sa[8][kGradChannels], sb[8][kGradChannels];
 #pragma unroll
@@ -141,19 +181,12 @@ __device__ __forceinline__ void log_replay(const DevGeom& g, GradAcc& A, double*
       }
       kb = key;
     }
-    const bool in_a = key == A.key;
+    const bool value = VALUE0 && e == 0;
+    const bool with_n = N_LAST && e == n - 1;
     float W[8];
     weights8(p[kWaveLanes], p[2 * kWaveLanes], p[3 * kWaveLanes], W);
-#pragma unroll
-    for (int ch = 0; ch < kGradChannels; ++ch) {
-      const float c = p[(4 + ch) * kWaveLanes];
-      const float ca = in_a ? c : 0.0f, cb = in_a ? 0.0f : c;
-#pragma unroll
-      for (int k = 0; k < 8; ++k) {
-        sa[k][ch] = fmaf(W[k], ca, sa[k][ch]);
-        sb[k][ch] = fmaf(W[k], cb, sb[k][ch]);
-      }
-    }
+    if (key == A.key) entry_add(sa, p, W, value, with_n);
+    else entry_add(sb, p, W, value, with_n);
   }
   acc_add(A, sa);
   if (kb >= 0) acc_replace(g, A, gacc, kb, sb);
@@ -252,7 +285,7 @@ __device__ __forceinline__ void eval_grad_adj(const DevGeom& g, const RayState& 
     Gb1 = gby * g.inv_sp[1];
     Gb2 = gbz * g.inv_sp[2];
   }
-  log_entry(lg, e, L, WITH_N ? nb : 0.0f, Gb0, Gb1, Gb2, 0.0f);
+  log_grad_entry(lg, e, L, WITH_N, nb, Gb0, Gb1, Gb2);
   // adjoint of the continuous index (zero along an axis held at an edge)
   const float nbe = WITH_N ? nb : 0.0f;
   const float xb0 = L.cl0 ? 0.0f : nbe * du.x + Gb0 * du.y + Gb1 * du.z + Gb2 * du.w;
@@ -307,7 +340,7 @@ __device__ __forceinline__ void eval_value_adj(const DevGeom& g, const RayState&
   float vn, dn0, dn1, dn2, vt, dt0, dt1, dt2;
   tri_deriv1(qn, L.u, L.v, L.w, vn, dn0, dn1, dn2);
   tri_deriv1(qt, L.u, L.v, L.w, vt, dt0, dt1, dt2);
-  log_entry(lg, e, L, nb, 0.0f, 0.0f, 0.0f, tb);
+  log_value_entry(lg, e, L, nb, tb);
   const float xb0 = L.cl0 ? 0.0f : nb * dn0 + tb * dt0;
   const float xb1 = L.cl1 ? 0.0f : nb * dn1 + tb * dt1;
   const float xb2 = L.cl2 ? 0.0f : nb * dn2 + tb * dt2;
@@ -559,7 +592,7 @@ __device__ __forceinline__ void step_adjoint(const AdjointArgs& aa, const RaySta
       if (jj == 0) { e1bx += ebx; e1by += eby; e1bz += ebz; }
       else { e2bx += ebx; e2by += eby; e2bz += ebz; }
     }
-    log_replay(g, A, gacc, lg, 7);
+    log_replay<true, false>(g, A, gacc, lg, 7);
     // e2 = t x e1
     tbx += e1y * e2bz - e1z * e2by; tby += e1z * e2bx - e1x * e2bz; tbz += e1x * e2by - e1y * e2bx;
     e1bx += e2by * uz - e2bz * uy; e1by += e2bz * ux - e2bx * uz; e1bz += e2bx * uy - e2by * ux;
@@ -635,10 +668,10 @@ __device__ __forceinline__ void step_adjoint(const AdjointArgs& aa, const RaySta
     // first stage at r_i (gradient and the value that set the step)
     eval_grad_adj<KIND, true>(g, R, C, lg, e0 + 3, O, 0.f, 0.f, 0.f, g1bx, g1by, g1bz, ne1_b, qx, qy, qz);
     rbx += qx; rby += qy; rbz += qz;
-    log_replay(g, A, gacc, lg, e0 + 4);
+    log_replay<!mag, true>(g, A, gacc, lg, e0 + 4);
   } else {
     pbx += hd * drbx; pby += hd * drby; pbz += hd * drbz;
-    log_replay(g, A, gacc, lg, 1);
+    log_replay<true, false>(g, A, gacc, lg, 1);
   }
   S.rbx = rbx; S.rby = rby; S.rbz = rbz;
   S.pbx = pbx; S.pby = pby; S.pbz = pbz;
@@ -782,7 +815,7 @@ __device__ __forceinline__ void adjoint_reverse_ray(const AdjointArgs& aa, int i
       make_origin<KIND>(R, O);
       float qx, qy, qz;
       eval_value_adj<KIND>(a.g, R, C, lg, 0, O, 0.f, 0.f, 0.f, ne_b, 0.0f, qx, qy, qz);
-      log_replay(a.g, A, aa.gacc, lg, 1);
+      log_replay<true, false>(a.g, A, aa.gacc, lg, 1);
     }
   }
 }
