@@ -71,6 +71,8 @@ def parse():
                     help="only run the adjoint / forward timing on the adjoint workload (for profiling)")
     ap.add_argument("--fit", type=int, default=0, metavar="ITERS",
                     help="study: recover a structured corona's ln n_e, ln T from its own maps (ITERS Adam steps)")
+    ap.add_argument("--spectrum", action="store_true",
+                    help="study: disc-centre T_b spectrum and beam-convolved maps of the structured workload")
     ap.add_argument("--modes", action="store_true",
                     help="study: straight line of sight vs refraction, magnification on/off, on the structured model")
     ap.add_argument("--batching", action="store_true",
@@ -227,11 +229,53 @@ def precision_study(n_pixels=4096, seconds_note=True):
     model.close()
 
 
+def spectrum_study():
+    """The disc-centre (< 0.5 R_sun) brightness-temperature spectrum of the
+    structured model, 512^2 over +/-3 R_sun, at 16 frequencies 40-800 MHz, traced
+    with refraction and magnification and along straight lines of sight
+    (Sec. 3.4.1 derives this spectrum from its synthetic maps), and the maps
+    convolved with the beam of a 15 km maximum baseline below 200 MHz and of
+    5 km above (the beams of the paper's figures in Sec. 3.3).  Reports the
+    spectra, the disc-centre mean of the convolved maps and the kernel times."""
+    import torch
+    from paper_2606_02413_amd import corona, rtsun as R
+    wl = corona.workload("structured")
+    model = R.Model.from_corona(wl.models(device="cuda")[0])
+    im = R.image_desc(wl.n_pix, wl.half_width)
+    freqs = corona.log_freqs(16)
+    fw = np.where(freqs < 200e6, R.beam_fwhm(freqs, 15e3), R.beam_fwhm(freqs, 5e3))
+    res = {"study": "spectrum", "workload": "structured model, 512^2 over +/-3 R_sun, 16 freq",
+           "MHz": [round(f / 1e6, 2) for f in freqs], "beam_fwhm_rsun": [round(float(x), 4) for x in fw]}
+
+    def timed(fn):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        out = fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return out, e0.elapsed_time(e1)
+
+    for name, kw in (("full", dict()), ("los", dict(refraction=False, magnification=False))):
+        prm = R.params(ds_max=wl.ds_max, n_floor=wl.n_floor, max_steps=wl.max_steps, **kw)
+        tb, ms = timed(lambda: R.trace_maps([model], freqs, im, prm, info=False, stats=False)["tb"][0])
+        R.disc_mean(tb, im, 0.5)
+        spec, ms_spec = timed(lambda: R.disc_mean(tb, im, 0.5))
+        R.beam_convolve(tb, im, fw)
+        conv, ms_beam = timed(lambda: R.beam_convolve(tb, im, fw))
+        res[name] = {"trace_ms": ms, "disc_mean_ms": ms_spec, "beam_ms": ms_beam,
+                     "tb_disc_centre_K": [round(float(x), 1) for x in spec.cpu().numpy()],
+                     "tb_disc_centre_convolved_K": [round(float(x), 1) for x in R.disc_mean(conv, im, 0.5).cpu().numpy()]}
+        progress(f"spectrum: {name} traced in {ms:.0f} ms, beam {ms_beam:.2f} ms")
+    print(json.dumps(res), flush=True)
+    model.close()
+
+
 def modes_study():
     """Straight lines of sight vs refractive tracing, and the magnification term
     on and off, on the structured workload's model (256x128x256, r 1-30 R_sun,
     8 active regions, seed 0), 512^2 image over +/-3 R_sun, at 40, 60, 80, 150,
-    280, 550 and 800 MHz (Sec. 3.3 compares these maps; Sec. 3.4 the term).
+    280, 550 and 800 MHz (Sec. 3.3 compares these maps and the effect of the term).
     Per frequency: the maximum T_b of each mode; the mean T_b on the disc centre
     (projected radius < 0.5 R_sun) and in the limb annulus (0.9-1.1 R_sun), and
     their ratio (limb brightening); the median and 99th percentile of
@@ -429,6 +473,9 @@ def main():
         return
     if args.modes:
         modes_study()
+        return
+    if args.spectrum:
+        spectrum_study()
         return
     if args.fit > 0:
         fit_study(args.fit)

@@ -257,6 +257,28 @@ rt_status rt_trace_adjoint(const rt_model* model, const double* freq_hz, int32_t
                            double* loss_out, float* grad_ln_ne, float* grad_ln_te, float* tb_out,
                            void* hip_stream);
 
+/* Maps convolved with a Gaussian beam (the interferometric beam the paper
+ * applies to its synthetic maps, Sec. 3.3).  maps_in, maps_out: DEVICE float32
+ * [n_maps][nv][nu] in the rt_trace_maps layout (pixel centres
+ * -half + (j + 1/2) 2 half / n), distinct.  fwhm: HOST [n_maps] beam full
+ * width at half maximum in R_sun (0: the map is copied).  The beam is sampled
+ * at pixel offsets, w(k) ~ exp(-k^2 / 2 sigma^2) with sigma = FWHM /
+ * (2 sqrt(2 ln 2)) in pixels along each axis, cut at |k| <= ceil(5 sigma) and
+ * normalised to sum 1; it is applied along u, then along v, with zero beyond
+ * the image edges.  n_maps <= 128.  Uses library scratch of the maps' size.
+ * Errors: RT_E_INVALID_ARG, RT_E_CAPACITY, RT_E_OUT_OF_MEMORY, RT_E_DEVICE. */
+rt_status rt_beam_convolve(const float* maps_in, float* maps_out, int32_t n_maps, int32_t nu, int32_t nv,
+                           double half_u, double half_v, const double* fwhm, void* hip_stream);
+
+/* Mean T_b of each map over the pixels whose centre lies within `radius`
+ * (R_sun) of the image centre: the disc-centre brightness-temperature spectrum
+ * when the maps are the frequencies of one model (Sec. 3.4.1).  maps: DEVICE
+ * float32 [n_maps][nv][nu]; mean_out: DEVICE double [n_maps] (0 when no pixel
+ * centre is inside).  Sums in FP64.  Errors: RT_E_INVALID_ARG, RT_E_CAPACITY,
+ * RT_E_DEVICE. */
+rt_status rt_disc_mean(const float* maps, int32_t n_maps, int32_t nu, int32_t nv, double half_u, double half_v,
+                       double radius, double* mean_out, void* hip_stream);
+
 const char* rt_status_string(rt_status s);
 const char* rt_last_error_message(void);
 uint32_t rt_abi_version(void);

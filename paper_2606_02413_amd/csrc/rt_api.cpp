@@ -77,6 +77,8 @@ struct DeviceScratch {
   size_t start_ne_cap = 0;
   void* adj_ws = nullptr;        // adjoint workspace (checkpoints, chunk records, channel adjoints), grown on demand
   size_t adj_bytes = 0;
+  float* blur_tmp = nullptr;     // intermediate maps of the beam convolution, grown on demand
+  size_t blur_bytes = 0;
   int n_cu = 0;
   rt_tuning tune{RT_ABI_VERSION, 64, 0, kXcds};  // launch tuning of the persistent trace
 };
@@ -696,6 +698,81 @@ rt_status rt_autotune(const rt_model* const* models, int32_t n_models, const dou
     if (best_ms) *best_ms = ms_best;
     if (default_ms) *default_ms = ms_default;
     return RT_OK;
+  } catch (...) {
+    return fail(RT_E_INTERNAL, "unexpected exception");
+  }
+}
+
+rt_status rt_beam_convolve(const float* maps_in, float* maps_out, int32_t n_maps, int32_t nu, int32_t nv,
+                           double half_u, double half_v, const double* fwhm, void* hip_stream) {
+  try {
+    if (!maps_in || !maps_out || !fwhm) return fail(RT_E_INVALID_ARG, "maps_in, maps_out and fwhm must not be NULL");
+    if (maps_in == maps_out) return fail(RT_E_INVALID_ARG, "maps_out must not alias maps_in");
+    if (n_maps < 1 || n_maps > kMaxBlurMaps) return fail(RT_E_INVALID_ARG, "n_maps must be 1..128");
+    if (nu < 1 || nv < 1) return fail(RT_E_INVALID_ARG, "nu, nv must be >= 1");
+    if (!(std::isfinite(half_u) && std::isfinite(half_v) && half_u > 0 && half_v > 0))
+      return fail(RT_E_INVALID_ARG, "half widths must be finite and > 0");
+    if ((long long)nu * nv * n_maps > (1ll << 31) - 1) return fail(RT_E_CAPACITY, "more than 2^31-1 pixels");
+    BlurArgs b{};
+    b.n_maps = n_maps; b.nu = nu; b.nv = nv;
+    const double pix[2] = {2.0 * half_u / nu, 2.0 * half_v / nv};
+    for (int m = 0; m < n_maps; ++m) {
+      if (!(std::isfinite(fwhm[m]) && fwhm[m] >= 0.0)) return fail(RT_E_INVALID_ARG, "fwhm must be finite and >= 0");
+      for (int ax = 0; ax < 2; ++ax) {
+        const double sigma = fwhm[m] / (2.0 * std::sqrt(2.0 * std::log(2.0))) / pix[ax];  // in pixels
+        const int len = ax == 0 ? nu : nv;
+        int R = sigma > 0.0 ? int(std::ceil(5.0 * sigma)) : 0;
+        if (R > len - 1) R = len - 1;
+        const double c = sigma > 0.0 ? 1.0 / (2.0 * sigma * sigma) : 0.0;
+        double norm = 0.0;
+        for (int k = -R; k <= R; ++k) norm += std::exp(-double(k) * k * c);
+        (ax == 0 ? b.radius_u : b.radius_v)[m] = R;
+        (ax == 0 ? b.inv2s2_u : b.inv2s2_v)[m] = float(c);
+        (ax == 0 ? b.inv_norm_u : b.inv_norm_v)[m] = float(1.0 / norm);
+      }
+    }
+    int dev = 0;
+    rt_status st = hip_check(hipGetDevice(&dev), "hipGetDevice");
+    if (st != RT_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    const size_t bytes = size_t(nu) * nv * n_maps * sizeof(float);
+    float* tmp = nullptr;
+    {
+      std::lock_guard<std::mutex> lk(g_scratch_mu);
+      DeviceScratch* sc = nullptr;
+      st = scratch_for(dev, &sc);
+      if (st != RT_OK) return st;
+      if (sc->blur_bytes < bytes) {
+        dev_free(sc->blur_tmp, sc->blur_bytes);
+        sc->blur_tmp = nullptr;
+        sc->blur_bytes = 0;
+        st = dev_alloc((void**)&sc->blur_tmp, bytes, "beam scratch");
+        if (st != RT_OK) return st;
+        sc->blur_bytes = bytes;
+      }
+      tmp = sc->blur_tmp;
+    }
+    return hip_check(launch_blur(b, maps_in, tmp, maps_out, s), "beam convolution");
+  } catch (...) {
+    return fail(RT_E_INTERNAL, "unexpected exception");
+  }
+}
+
+rt_status rt_disc_mean(const float* maps, int32_t n_maps, int32_t nu, int32_t nv, double half_u, double half_v,
+                       double radius, double* mean_out, void* hip_stream) {
+  try {
+    if (!maps || !mean_out) return fail(RT_E_INVALID_ARG, "maps and mean_out must not be NULL");
+    if (n_maps < 1 || nu < 1 || nv < 1) return fail(RT_E_INVALID_ARG, "n_maps, nu, nv must be >= 1");
+    if (!(std::isfinite(half_u) && std::isfinite(half_v) && half_u > 0 && half_v > 0))
+      return fail(RT_E_INVALID_ARG, "half widths must be finite and > 0");
+    if (!(std::isfinite(radius) && radius > 0)) return fail(RT_E_INVALID_ARG, "radius must be finite and > 0");
+    if ((long long)nu * nv * n_maps > (1ll << 31) - 1) return fail(RT_E_CAPACITY, "more than 2^31-1 pixels");
+    DiscArgs d{};
+    d.n_maps = n_maps; d.nu = nu; d.nv = nv;
+    d.half_u = half_u; d.half_v = half_v;
+    d.pix_u = 2.0 * half_u / nu; d.pix_v = 2.0 * half_v / nv;
+    d.radius2 = radius * radius;
+    return hip_check(launch_disc_mean(d, maps, mean_out, static_cast<hipStream_t>(hip_stream)), "disc mean");
   } catch (...) {
     return fail(RT_E_INTERNAL, "unexpected exception");
   }

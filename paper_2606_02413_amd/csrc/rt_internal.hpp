@@ -91,6 +91,21 @@ struct AdjointArgs {
   int n_rays;                 // 64 n_tiles; ray rid = 64 (tile - tile0) + lane
 };
 
+// Map post-processing (rt_maps.hip).
+constexpr int kMaxBlurMaps = 128;   // maps per beam-convolution call
+struct BlurArgs {
+  int n_maps, nu, nv;
+  int radius_u[kMaxBlurMaps], radius_v[kMaxBlurMaps];          // taps |k| <= radius
+  float inv2s2_u[kMaxBlurMaps], inv2s2_v[kMaxBlurMaps];        // 1 / (2 sigma^2), sigma in pixels
+  float inv_norm_u[kMaxBlurMaps], inv_norm_v[kMaxBlurMaps];    // 1 / sum of the taps
+};
+struct DiscArgs {
+  int n_maps, nu, nv;
+  double half_u, half_v, pix_u, pix_v, radius2;
+};
+hipError_t launch_blur(const BlurArgs& b, const float* in, float* tmp, float* out, hipStream_t s);
+hipError_t launch_disc_mean(const DiscArgs& d, const float* maps, double* out, hipStream_t s);
+
 // Launchers (rt_kernels.hip).
 hipError_t launch_pack(const DevGeom& g, const float* ne, const float* te, float4* nfg, float* te_out,
                        hipStream_t s);
@@ -113,3 +128,4 @@ int adjoint_blocks_per_cu(int kind);
 static_assert(sizeof(rt_ray_info) == 32, "rt_ray_info is 32 bytes");
 static_assert(sizeof(rt_trace_stats) == 40, "rt_trace_stats is 40 bytes");
 static_assert(sizeof(rt::AdjointArgs) <= 4096, "kernel arguments fit the 4 KiB argument segment");
+static_assert(sizeof(rt::BlurArgs) <= 4096, "kernel arguments fit the 4 KiB argument segment");

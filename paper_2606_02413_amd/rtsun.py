@@ -111,6 +111,11 @@ def lib():
                                   C.POINTER(Params), C.c_int32, C.POINTER(Tuning), C.POINTER(C.c_double),
                                   C.POINTER(C.c_double), vp]
         L.rt_autotune.restype = C.c_int
+        L.rt_beam_convolve.argtypes = [vp, vp, C.c_int32, C.c_int32, C.c_int32, C.c_double, C.c_double,
+                                       C.POINTER(C.c_double), vp]
+        L.rt_beam_convolve.restype = C.c_int
+        L.rt_disc_mean.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32, C.c_double, C.c_double, C.c_double, vp, vp]
+        L.rt_disc_mean.restype = C.c_int
         _lib = L
     return _lib
 
@@ -318,6 +323,40 @@ def autotune(models, freqs, image, prm, *, max_freqs=8, cache=None, stream=None)
             json.dump(table, fh, indent=1, sort_keys=True)
         os.replace(tmp, cache)
     return dict(rec, key=key, cached=False)
+
+
+def beam_fwhm(freqs, baseline_m):
+    """Beam FWHM in R_sun of an interferometer with maximum baseline `baseline_m`
+    (metres): lambda / B radians, over the angle 1 R_sun subtends at 1 au."""
+    lam = 299792458.0 / np.asarray(freqs, dtype=np.float64)
+    return (lam / float(baseline_m)) / (6.957e8 / 1.495978707e11)
+
+
+def beam_convolve(maps, image, fwhm, *, stream=None, out=None):
+    """Maps [..., nv, nu] (float32 device tensor) convolved with Gaussian beams of
+    the given FWHM (R_sun, one per map in the flattened leading dimensions)."""
+    import torch
+    x = maps.contiguous()
+    n_maps = x.numel() // (image.nu * image.nv)
+    fw = np.ascontiguousarray(np.broadcast_to(np.asarray(fwhm, dtype=np.float64), (n_maps,)))
+    y = torch.empty_like(x) if out is None else out
+    _check(lib().rt_beam_convolve(C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()), n_maps, image.nu, image.nv,
+                                  image.half_u, image.half_v, fw.ctypes.data_as(C.POINTER(C.c_double)),
+                                  _stream_ptr(stream)))
+    return y
+
+
+def disc_mean(maps, image, radius=0.5, *, stream=None):
+    """Mean T_b within `radius` R_sun of the image centre of each map [..., nv, nu]
+    (float64 device tensor of the leading shape)."""
+    import torch
+    x = maps.contiguous()
+    lead = x.shape[:-2]
+    n_maps = x.numel() // (image.nu * image.nv)
+    y = torch.empty(n_maps, dtype=torch.float64, device=x.device)
+    _check(lib().rt_disc_mean(C.c_void_p(x.data_ptr()), n_maps, image.nu, image.nv, image.half_u, image.half_v,
+                              float(radius), C.c_void_p(y.data_ptr()), _stream_ptr(stream)))
+    return y.reshape(lead)
 
 
 def capture_trace_maps(models, freqs, image, prm, *, info=False, stats=True):

@@ -119,6 +119,24 @@ def test_tuning_defaults_and_validation(R):
     assert L.rt_autotune(h, 1, f, 1, C.byref(im), C.byref(plain), 4, None, None, None, None) == 1
 
 
+def test_map_postprocessing_validation(R):
+    L = R.lib()
+    fw = (C.c_double * 2)(0.1, 0.1)
+    buf = C.c_void_p(16)
+    other = C.c_void_p(32)
+    assert L.rt_beam_convolve(None, other, 2, 8, 8, 1.0, 1.0, fw, None) == 1
+    assert L.rt_beam_convolve(buf, buf, 2, 8, 8, 1.0, 1.0, fw, None) == 1        # in place
+    assert L.rt_beam_convolve(buf, other, 0, 8, 8, 1.0, 1.0, fw, None) == 1
+    assert L.rt_beam_convolve(buf, other, 129, 8, 8, 1.0, 1.0, fw, None) == 1
+    assert L.rt_beam_convolve(buf, other, 2, 8, 8, 0.0, 1.0, fw, None) == 1
+    bad = (C.c_double * 2)(0.1, -1.0)
+    assert L.rt_beam_convolve(buf, other, 2, 8, 8, 1.0, 1.0, bad, None) == 1
+    assert L.rt_disc_mean(None, 1, 8, 8, 1.0, 1.0, 0.5, other, None) == 1
+    assert L.rt_disc_mean(buf, 1, 8, 8, 1.0, 1.0, 0.0, other, None) == 1
+    assert L.rt_disc_mean(buf, 1, 0, 8, 1.0, 1.0, 0.5, other, None) == 1
+    assert abs(R.beam_fwhm([40e6], 15e3)[0] - 0.1074) < 1e-3   # 7.49 m / 15 km = 5.0e-4 rad
+
+
 def test_binding_fails_loudly_without_library(R, monkeypatch):
     monkeypatch.setattr(R, "_lib", None)
     monkeypatch.setattr(R, "LIB_PATH", "/nonexistent/librtsun.so")
