@@ -198,6 +198,8 @@ struct Params {
   double eta;                  // perturb_ratio
   double tb_inner, tb_sky;
   double dp_rtol, dp_atol;
+  int32_t carried_tube;        // 1: tube area from two neighbour rays carried along the whole ray
+  int32_t _pad;
 };
 
 struct Image {
@@ -526,6 +528,31 @@ RayOut<S> trace_rk4(const Medium& m, const Src& src, const Params& P, double f,
   }
   const double L0 = vnorm(cross(r, p));
   double bdrift = 0.0, hdrift = 0.0;
+  // Carried tube: two neighbour rays launched eps = eta ds_max away from the
+  // central ray across its initial direction (the Eq. 6 basis of d), each with
+  // the wavevector n(start) d, stepped with the central ray's dt for the whole
+  // ray; the tube cross-section at a step point is S = |(dr_a x dr_b) . p_hat|
+  // with dr the separations from the central ray at equal t, and ln M of a step
+  // is ln(S_{i+1} / S_i), so that the sum over the ray is ln(S_end / S_0).
+  const bool carried = mag && P.carried_tube != 0;
+  V3<S> ra, pa, rb, pb;
+  S ln_s_prev(0.0);
+  auto tube_ln_s = [&](const V3<S>& rc, const V3<S>& pc, const V3<S>& xa, const V3<S>& xb) {
+    V3<S> ph = (S(1.0) / norm(pc)) * pc;
+    return log(fabs(dot(cross(xa - rc, xb - rc), ph)));
+  };
+  if (carried) {
+    V3<S> a = (std::fabs(val(d.z)) > 0.9) ? V3<S>{S(0.0), S(1.0), S(0.0)} : V3<S>{S(0.0), S(0.0), S(1.0)};
+    V3<S> c1 = cross(a, d);
+    V3<S> e1 = (S(1.0) / norm(c1)) * c1;
+    V3<S> e2 = cross(d, e1);
+    const S eps(P.eta * P.ds_max);
+    ra = r + eps * e1;
+    rb = r + eps * e2;
+    pa = index_from_ne(eval_medium(m, src, ra, false).ne, xf) * d;
+    pb = index_from_ne(eval_medium(m, src, rb, false).ne, xf) * d;
+    ln_s_prev = tube_ln_s(r, p, ra, rb);
+  }
   std::vector<Segment<S>> segs;
   int code = RUNNING, n_steps = 0;
   double rmin = vnorm(r), lam_last = 1.0;
@@ -560,7 +587,13 @@ RayOut<S> trace_rk4(const Medium& m, const Src& src, const Params& P, double f,
     S ds = norm(dr);
     V3<S> that = (S(1.0) / ds) * dr;
     S lnM(0.0);
-    if (mag) {
+    if (carried) {
+      rk4_step(m, src, xf, refr, dt, ra, pa);
+      rk4_step(m, src, xf, refr, dt, rb, pb);
+      const S ln_s = tube_ln_s(r1, p1, ra, rb);
+      lnM = ln_s - ln_s_prev;
+      ln_s_prev = ln_s;
+    } else if (mag) {
       // Reference axis least aligned with t: z unless |t_z| is close to 1.
       V3<S> a = (std::fabs(val(that.z)) > 0.9) ? V3<S>{S(0.0), S(1.0), S(0.0)} : V3<S>{S(0.0), S(0.0), S(1.0)};
       V3<S> c1 = cross(a, that);                          // Eq. 6
