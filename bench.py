@@ -75,6 +75,8 @@ def parse():
                     help="study: disc-centre T_b spectrum and beam-convolved maps of the structured workload")
     ap.add_argument("--modes", action="store_true",
                     help="study: straight line of sight vs refraction, magnification on/off, on the structured model")
+    ap.add_argument("--tube", action="store_true",
+                    help="carried ray tube vs the step-wise estimate: ln S convergence, T_b effect, cost")
     ap.add_argument("--batching", action="store_true",
                     help="only run the batching study (batched vs plain on the 4-model 64-frequency workload)")
     ap.add_argument("--precision", action="store_true",
@@ -329,6 +331,69 @@ def modes_study():
     model.close()
 
 
+def tube_study():
+    """Carried ray tube vs the step-wise estimate of Eqs. 5-11 on the structured
+    workload's model (256x128x256, r 1-30 R_sun, seed 0), 512^2 image over
+    +/-3 R_sun, the eight frequencies 40-800 MHz, n_floor 0.1, at ds_max 0.01
+    and 0.005.  Per frequency and tube: the median |ln S_end| over rays; the
+    median |ln S_end(ds/2) - ln S_end(ds)| / |ln S_end(ds/2)| over rays with
+    |ln S_end| > 0.1 (the step-wise value is proportional to the step, the
+    carried one converges); and the median and 99th percentile over pixels
+    within 2 R_sun of |T_b(tube) - T_b(no tube term)| / T_b(no tube term), the
+    size of the magnification term in the maps.  Each trace is timed (the
+    carried tube always runs as one launch per image).  Prints one JSON line."""
+    import torch
+    from paper_2606_02413_amd import corona, rtsun as R
+    wl = corona.workload("structured")
+    model = R.Model.from_corona(wl.models(device="cuda")[0])
+    n, hw = wl.n_pix, wl.half_width
+    im = R.image_desc(n, hw)
+    freqs = wl.freqs
+    c = (np.arange(n) + 0.5) * (2 * hw / n) - hw
+    inner = np.hypot(c[None, :], c[:, None]) < 2.0
+    runs = {}
+    for ds in (wl.ds_max, 0.5 * wl.ds_max):
+        for name, kw in (("none", dict(magnification=False, plain=True)), ("stepwise", dict(plain=True)),
+                         ("carried", dict(carried_tube=True))):
+            prm = R.params(ds_max=ds, n_floor=wl.n_floor, max_steps=wl.max_steps, **kw)
+            out = R.trace_maps([model], freqs, im, prm, info=True, stats=True)
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            R.trace_maps([model], freqs, im, prm, info=True, stats=True, out=out)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1)
+            steps = int(R.decode_stats(out["stats"])["ray_steps"])
+            info = R.decode_info(out["info"][0])
+            runs[name, ds] = dict(ms=ms, steps=steps, tb=out["tb"][0].double().cpu().numpy(),
+                                  lns=info["ln_s_end"].astype(np.float64), code=info["code"])
+            progress(f"tube: {name} ds {ds} {ms:.0f} ms, {steps / ms * 1e-6:.3f} G ray-steps/s")
+    h0, h1 = wl.ds_max, 0.5 * wl.ds_max
+    rows = []
+    for k, f in enumerate(freqs):
+        row = {"MHz": round(float(f) / 1e6, 1)}
+        ref = runs["none", h0]["tb"][k]
+        for name in ("stepwise", "carried"):
+            a, b = runs[name, h0], runs[name, h1]
+            la, lb = a["lns"][k].ravel(), b["lns"][k].ravel()
+            live = (a["code"][k].ravel() != 3) & (a["code"][k].ravel() == b["code"][k].ravel())
+            row[f"median_abs_ln_s_end_{name}"] = float(np.median(np.abs(la[live])))
+            big = live & (np.abs(lb) > 0.1)
+            row[f"halving_change_{name}"] = float(np.median(np.abs(lb[big] - la[big]) / np.abs(lb[big]))) if big.any() else None
+            d = np.abs(a["tb"][k] - ref)[inner] / np.maximum(ref[inner], 1.0)
+            row[f"tb_effect_{name}_median"] = float(np.median(d))
+            row[f"tb_effect_{name}_p99"] = float(np.quantile(d, 0.99))
+        rows.append(row)
+    timing = {f"{name}_ds{ds:g}": {"ms": round(r["ms"], 1), "ray_steps": r["steps"],
+                                   "g_ray_steps_per_s": round(r["steps"] / r["ms"] * 1e-6, 3)}
+              for (name, ds), r in runs.items()}
+    print(json.dumps({"study": "carried_tube", "workload": "structured model, 512^2 over +/-3 R_sun, 8 frequencies",
+                      "timing": timing, "per_frequency": rows}), flush=True)
+    model.close()
+
+
 def fit_study(iters):
     """Coronal fitting through the adjoint: the maps of a structured corona
     (128x64x128, r 1-30 R_sun, random field and 8 active regions, seed 0) at the
@@ -479,6 +544,9 @@ def main():
         return
     if args.fit > 0:
         fit_study(args.fit)
+        return
+    if args.tube:
+        tube_study()
         return
     if args.adjoint_only:
         import torch

@@ -126,6 +126,18 @@ enum {
   RT_SCHED_PLAIN = 1u << 3,        /* one launch per (model, frequency) image instead of
                                       one persistent launch over all of them */
   RT_DETERMINISTIC_GRAD = 1u << 4, /* reserved (rt_trace_adjoint: RT_E_UNSUPPORTED) */
+  RT_CARRIED_TUBE = 1u << 5,       /* the ray-tube cross-section S of Eqs. 2-3 from two
+                                      neighbour rays launched perturb_ratio*ds_max away
+                                      across the initial direction (Eq. 6 basis) and
+                                      stepped beside the ray for its whole length, in
+                                      place of the per-step retrace of Eqs. 7-11:
+                                      ln M of a step = ln(S_{i+1}/S_i), S = |(dr_a x dr_b)
+                                      . p/|p||, dr the separations at equal t.  Needs
+                                      RT_USE_REFRACTION | RT_USE_MAGNIFICATION
+                                      (RT_E_INVALID_ARG otherwise); mixed precision only
+                                      (RT_E_UNSUPPORTED with RT_PREC_ALL_FP32); always one
+                                      launch per image; rt_autotune: RT_E_INVALID_ARG;
+                                      rt_trace_adjoint: RT_E_UNSUPPORTED */
   RT_TEST_NO_ABSORPTION = 1u << 30 /* kappa = 0 (tests of I*S = const, Eq. 1) */
 };
 

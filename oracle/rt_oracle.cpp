@@ -215,6 +215,7 @@ struct Result {
   double lam_last;
   double bouguer_drift;        // max |(|r x p| - L0)| / L0 over accepted steps
   double ham_drift;            // max abs(|p|^2 + X - 1) over accepted steps
+  double ln_s_min;             // smallest ln(S/S_0) over the step points (0 at the start)
   int32_t n_steps, code, flags, _pad;
 };
 
@@ -487,7 +488,7 @@ template <class S> struct Segment { S dtau, gamma, te; };
 
 template <class S> struct RayOut {
   S tb, tau, ln_s;
-  double r_min, lam_last, bouguer_drift, ham_drift;
+  double r_min, lam_last, bouguer_drift, ham_drift, ln_s_min;
   V3<double> exit_pos;
   int n_steps, code, flags;
 };
@@ -527,7 +528,7 @@ RayOut<S> trace_rk4(const Medium& m, const Src& src, const Params& P, double f,
     p = d;
   }
   const double L0 = vnorm(cross(r, p));
-  double bdrift = 0.0, hdrift = 0.0;
+  double bdrift = 0.0, hdrift = 0.0, lns_min = 0.0;
   // Carried tube: two neighbour rays launched eps = eta ds_max away from the
   // central ray across its initial direction (the Eq. 6 basis of d), each with
   // the wavevector n(start) d, stepped with the central ray's dt for the whole
@@ -629,6 +630,7 @@ RayOut<S> trace_rk4(const Medium& m, const Src& src, const Params& P, double f,
     segs.push_back({dtau, gamma, sm.te});
     tau = tau + dtau;
     lns = lns + lam * lnM;
+    lns_min = std::min(lns_min, val(lns));
     s_arc = s_arc + lam * ds;
     if (path && path_len && *path_len < path_cap) {
       V3<S> pe = r + lam * dr;
@@ -672,6 +674,7 @@ RayOut<S> trace_rk4(const Medium& m, const Src& src, const Params& P, double f,
   out.flags = 0;
   out.bouguer_drift = bdrift;
   out.ham_drift = hdrift;
+  out.ln_s_min = lns_min;
   if ((code == EXIT_OUTER || code == HIT_INNER) && (lam_last < 1e-4 || lam_last > 1.0 - 1e-4))
     out.flags |= MARGINAL;
   // Near the polar axis of a spherical grid the theta rows are clamped and the
@@ -825,7 +828,7 @@ static RayOut<double> trace_dp54(const Medium& m, const Params& P, double f, con
   for (int i = int(segs.size()) - 1; i >= 0; --i) T = segment_apply(segs[size_t(i)], T);
   out.tb = T; out.tau = tau; out.ln_s = 0; out.r_min = rmin; out.lam_last = lam_last;
   out.exit_pos = exitp; out.n_steps = n_steps; out.code = code; out.flags = 0;
-  out.bouguer_drift = bdrift; out.ham_drift = hdrift;
+  out.bouguer_drift = bdrift; out.ham_drift = hdrift; out.ln_s_min = 0.0;
   return out;
 }
 
@@ -863,7 +866,7 @@ static void fill_result(const RayOut<double>& ro, Result& r) {
   r.tb = ro.tb; r.tau = ro.tau; r.ln_s_end = ro.ln_s; r.r_min = ro.r_min;
   r.exit_pos[0] = ro.exit_pos.x; r.exit_pos[1] = ro.exit_pos.y; r.exit_pos[2] = ro.exit_pos.z;
   r.lam_last = ro.lam_last; r.n_steps = ro.n_steps; r.code = ro.code; r.flags = ro.flags;
-  r.bouguer_drift = ro.bouguer_drift; r.ham_drift = ro.ham_drift; r._pad = 0;
+  r.bouguer_drift = ro.bouguer_drift; r.ham_drift = ro.ham_drift; r.ln_s_min = ro.ln_s_min; r._pad = 0;
 }
 
 static RayOut<double> trace_any(const Medium& m, const Params& P, double f, const V3<double>& r0,

@@ -234,8 +234,13 @@ rt_status prepare_call(const rt_model* const* models, int32_t n_models, const do
   const rt_params& P = *params;
   if (P.abi_version != RT_ABI_VERSION) return fail(RT_E_INVALID_ARG, "params->abi_version mismatch");
   const uint32_t known = RT_USE_MAGNIFICATION | RT_USE_REFRACTION | RT_PREC_ALL_FP32 | RT_SCHED_PLAIN |
-                         RT_DETERMINISTIC_GRAD | RT_TEST_NO_ABSORPTION;
+                         RT_DETERMINISTIC_GRAD | RT_CARRIED_TUBE | RT_TEST_NO_ABSORPTION;
   if (P.flags & ~known) return fail(RT_E_INVALID_ARG, "unknown flag bits");
+  if (P.flags & RT_CARRIED_TUBE) {
+    if ((P.flags & (RT_USE_REFRACTION | RT_USE_MAGNIFICATION)) != (RT_USE_REFRACTION | RT_USE_MAGNIFICATION))
+      return fail(RT_E_INVALID_ARG, "RT_CARRIED_TUBE needs RT_USE_REFRACTION and RT_USE_MAGNIFICATION");
+    if (P.flags & RT_PREC_ALL_FP32) return fail(RT_E_UNSUPPORTED, "RT_CARRIED_TUBE runs in mixed precision only");
+  }
   if (!(std::isfinite(P.ds_max) && P.ds_max > 0.0)) return fail(RT_E_INVALID_ARG, "ds_max must be > 0");
   if (!(std::isfinite(P.n_floor) && P.n_floor > 0.0 && P.n_floor <= 1.0)) return fail(RT_E_INVALID_ARG, "n_floor must be in (0, 1]");
   if (P.max_steps < 1) return fail(RT_E_INVALID_ARG, "max_steps must be >= 1");
@@ -503,7 +508,7 @@ rt_status rt_trace_maps(const rt_model* const* models, int32_t n_models, const d
     }
     const rt_params& P = *params;
     const bool mixed = (P.flags & RT_PREC_ALL_FP32) == 0;
-    if (P.flags & RT_SCHED_PLAIN) {
+    if (P.flags & (RT_SCHED_PLAIN | RT_CARRIED_TUBE)) {
       const int waves = a.tiles_per_image;
       const int blocks = (waves + 3) / 4;
       for (int mi = 0; mi < n_models; ++mi)
@@ -595,7 +600,8 @@ rt_status rt_autotune(const rt_model* const* models, int32_t n_models, const dou
     if (!models || n_models < 1 || !models[0]) return fail(RT_E_INVALID_ARG, "need at least one model");
     if (!freq_hz || n_freq < 1) return fail(RT_E_INVALID_ARG, "need at least one frequency");
     if (!image || !params) return fail(RT_E_INVALID_ARG, "image/params is NULL");
-    if (params->flags & RT_SCHED_PLAIN) return fail(RT_E_INVALID_ARG, "the tuning applies to the persistent trace");
+    if (params->flags & (RT_SCHED_PLAIN | RT_CARRIED_TUBE))
+      return fail(RT_E_INVALID_ARG, "the tuning applies to the persistent trace");
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
     const int dev = models[0]->device;
     rt_status st = hip_check(hipSetDevice(dev), "hipSetDevice");
@@ -791,6 +797,8 @@ rt_status rt_trace_adjoint(const rt_model* model, const double* freq_hz, int32_t
       return fail(RT_E_UNSUPPORTED, "RT_TEST_NO_ABSORPTION is a forward-only test mode");
     if (params && (params->flags & RT_DETERMINISTIC_GRAD))
       return fail(RT_E_UNSUPPORTED, "RT_DETERMINISTIC_GRAD is not supported by this build");
+    if (params && (params->flags & RT_CARRIED_TUBE))
+      return fail(RT_E_UNSUPPORTED, "the adjoint differentiates the step-wise tube estimate only");
     if (params && params->checkpoint_every < 0) return fail(RT_E_INVALID_ARG, "checkpoint_every must be >= 0");
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
     TraceArgs a{};

@@ -156,8 +156,11 @@ __device__ __forceinline__ int xcd_remap(int bid, int nblocks) {
 // ---------------------------------------------------------------------------
 // One launch per (model, frequency) image: a wave traces one 8x8 pixel tile.
 // ---------------------------------------------------------------------------
-template <bool MIXED, int KIND>
-__global__ __launch_bounds__(256, 2) void k_trace_plain(TraceArgs a) {
+// MODE kModeCarried: the ray tube is carried along the whole ray by two
+// neighbour rays (launched across the initial direction) instead of being
+// retraced at every step.
+template <bool MIXED, int KIND, int MODE = kModeFlags>
+__global__ __launch_bounds__(256, MODE == kModeCarried ? 1 : 2) void k_trace_plain(TraceArgs a) {
   __shared__ float4 lds_c[4][8][kWaveLanes];
   __shared__ float lds_t[4][8][kWaveLanes];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -173,9 +176,10 @@ __global__ __launch_bounds__(256, 2) void k_trace_plain(TraceArgs a) {
     C.c = &lds_c[wave][0][lane];
     C.t = &lds_t[wave][0][lane];
     if (init_ray(a, a.image0, i * a.nu + j, R, C)) {
+      if constexpr (MODE == kModeCarried) init_tube<KIND>(a, R, C);
       int code;
       do {
-        code = ray_step<MIXED, KIND>(a, R, C);
+        code = ray_step<MIXED, KIND, MODE>(a, R, C);
       } while (code == kRunning);
       finish_ray(a, R);
       lane_stats_add(st, R.n, code);
@@ -342,7 +346,11 @@ hipError_t launch_fill_u32(unsigned* p, unsigned val, long long n, hipStream_t s
 
 template <bool MIXED, int KIND>
 static hipError_t launch_one(const TraceArgs& a, bool plain, int blocks, hipStream_t s) {
-  if (plain) hipLaunchKernelGGL((k_trace_plain<MIXED, KIND>), dim3(blocks), dim3(256), 0, s, a);
+  if (a.flags & RT_CARRIED_TUBE) {
+    // carried tubes: mixed precision, one launch per image
+    if (!MIXED || !plain) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_trace_plain<true, KIND, kModeCarried>), dim3(blocks), dim3(256), 0, s, a);
+  } else if (plain) hipLaunchKernelGGL((k_trace_plain<MIXED, KIND>), dim3(blocks), dim3(256), 0, s, a);
   else hipLaunchKernelGGL((k_trace_persistent<MIXED, KIND>), dim3(blocks), dim3(256), 0, s, a);
   return hipGetLastError();
 }

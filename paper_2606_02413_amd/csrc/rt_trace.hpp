@@ -421,6 +421,10 @@ struct RayState {
   int id;                   // flat ray index
   int code;
   int path_slot, path_len;
+  // carried tube (kModeCarried only): separations of the two neighbour rays
+  // from this ray at equal t, position and wavevector, and ln S at r_i
+  double nb_r[2][3], nb_p[2][3];
+  double tube_ln_s;
 };
 
 // Chord-sphere crossing: root in [0, 1] of |o + lam d|^2 = R^2 (outward: larger root).
@@ -585,6 +589,41 @@ __device__ __forceinline__ bool init_ray(const TraceArgs& a, int img, int pix, R
   return true;
 }
 
+// Carried tube at the launch: neighbours eps = eta ds_max away across the launch
+// direction d = -o (the Eq. 6 basis of d), each with the wavevector n(start) d;
+// ln S at the start point.
+template <int KIND>
+__device__ __forceinline__ void init_tube(const TraceArgs& a, RayState& R, CellCache& C) {
+  const double dx = -a.o[0], dy = -a.o[1], dz = -a.o[2];
+  double c1x, c1y, c1z;
+  if (fabs(dz) > 0.9) { c1x = dz; c1y = 0.0; c1z = -dx; }   // y x d
+  else { c1x = -dy; c1y = dx; c1z = 0.0; }                  // z x d
+  const double ci = rsqrt64(c1x * c1x + c1y * c1y + c1z * c1z);
+  const double e[2][3] = {{c1x * ci, c1y * ci, c1z * ci},
+                          {dy * c1z * ci - dz * c1y * ci, dz * c1x * ci - dx * c1z * ci, dx * c1y * ci - dy * c1x * ci}};
+  const double eps = a.ds_max_d * double(a.eta);
+  StepOrigin O;
+  make_origin<KIND>(R, O);
+  // the wavevector difference (n_j - n_0) d from the difference of n_e, so that
+  // it is not lost in the rounding of n (n_j - n_0 = -Xf (ne_j - ne_0) / (n_j + n_0))
+  float ne0, te0;
+  eval_value<KIND>(a.g, R.nfg, R.te, C, O, 0.f, 0.f, 0.f, ne0, te0);
+  const double xf = -2.0 * R.cfd;
+  const double n0 = sqrt64(fmax(1.0 - xf * double(ne0), 0.0));
+  for (int j = 0; j < 2; ++j) {
+    float ne, te;
+    eval_value<KIND>(a.g, R.nfg, R.te, C, O, float(eps * e[j][0]), float(eps * e[j][1]), float(eps * e[j][2]), ne, te);
+    const double nj = sqrt64(fmax(1.0 - xf * double(ne), 0.0));
+    const double dn = (nj + n0) > 0.0 ? -xf * (double(ne) - double(ne0)) * rcp64(nj + n0) : 0.0;
+    for (int k = 0; k < 3; ++k) {
+      R.nb_r[j][k] = eps * e[j][k];
+      R.nb_p[j][k] = dn * (k == 0 ? dx : k == 1 ? dy : dz);
+    }
+  }
+  // S_0 = |(eps e1 x eps e2) . d| = eps^2
+  R.tube_ln_s = log(eps * eps);
+}
+
 __device__ __forceinline__ void finish_ray(const TraceArgs& a, const RayState& R) {
   const double tbc = (R.code == kHit) ? a.tb_inner : a.tb_sky;
   const float trans = __builtin_amdgcn_exp2f(-1.44269504089f * float(R.lam_tot));
@@ -620,7 +659,7 @@ __device__ __forceinline__ float segment_phi(float x) {
 }
 
 // Tracing mode of ray_step: from the call's flags, or fixed at compile time.
-enum : int { kModeFlags = 0, kModeLos = 1, kModeNoMag = 2, kModeFull = 3 };
+enum : int { kModeFlags = 0, kModeLos = 1, kModeNoMag = 2, kModeFull = 3, kModeCarried = 4 };
 
 // One central RK4 step with its two perturbed retraces, termination test and
 // transfer segment.  Returns the termination code (kRunning to continue); on
@@ -633,6 +672,7 @@ __device__ __forceinline__ int ray_step(const TraceArgs& a, RayState& R, CellCac
   using Real = typename RealOf<MIXED>::T;
   const bool refr = (MODE == kModeFlags) ? (a.flags & RT_USE_REFRACTION) != 0 : (MODE != kModeLos);
   const bool mag = (MODE == kModeFlags) ? refr && (a.flags & RT_USE_MAGNIFICATION) != 0 : (MODE == kModeFull);
+  constexpr bool carried = MODE == kModeCarried;
 
   // All evaluation points of this step are r_i + (FP32 offset).
   StepOrigin O;
@@ -643,13 +683,15 @@ __device__ __forceinline__ int ray_step(const TraceArgs& a, RayState& R, CellCac
   double drx, dry, drz, dpx = 0.0, dpy = 0.0, dpz = 0.0;
   float d2x = 0.f, d2y = 0.f, d2z = 0.f, d3x = 0.f, d3y = 0.f, d3z = 0.f;
   float F1x = 0.f, F1y = 0.f, F1z = 0.f, F2x = 0.f, F2y = 0.f, F2z = 0.f, F3x = 0.f, F3y = 0.f, F3z = 0.f;
+  float sx = 0.f, sy = 0.f, sz = 0.f;                 // g1 + g2 + g3
+  float tx = 0.f, ty = 0.f, tz = 0.f;                 // g1 + 2 g2 + 2 g3 + g4
   if (refr) {
     // Stage 1 at r_i also sets the step: dt = ds_max / max(n(r_i), n_floor).
     float ne, gx, gy, gz;
     eval_grad<KIND>(a.g, R.nfg, R.te, C, O, 0.f, 0.f, 0.f, ne, gx, gy, gz);
     F1x = R.cf * gx; F1y = R.cf * gy; F1z = R.cf * gz;
-    float sx = gx, sy = gy, sz = gz;                  // g1 + g2 + g3
-    float tx = gx, ty = gy, tz = gz;                  // g1 + 2 g2 + 2 g3 + g4
+    sx = gx; sy = gy; sz = gz;
+    tx = gx; ty = gy; tz = gz;
     const float n2 = 1.0f - R.xff * ne;
     const float ni = n2 > 0.f ? sqrt_fast(n2) : 0.f;
     if (TAPE && tp) {
@@ -691,6 +733,41 @@ __device__ __forceinline__ int ray_step(const TraceArgs& a, RayState& R, CellCac
     h = a.ds_max;
     hd = a.ds_max_d;
     drx = hd * R.px; dry = hd * R.py; drz = hd * R.pz;
+  }
+  if constexpr (carried) {
+    // The two neighbour rays take the same RK4 step from r_i + dr_j with wavevector
+    // p_i + dp_j; their stages are evaluated at FP32 offsets from r_i, and their
+    // separations advance by the differences of the increments (FP64):
+    // d(dr_j) = h dp_j + h^2/6 cf (s_j - s), d(dp_j) = h/6 cf (t_j - t).
+    const float hh = 0.5f * h;
+    const double c6 = R.cfd * hd * (1.0 / 6.0);
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const double qx = R.px + R.nb_p[j][0], qy = R.py + R.nb_p[j][1], qz = R.pz + R.nb_p[j][2];
+      const float bx = float(R.nb_r[j][0]), by = float(R.nb_r[j][1]), bz = float(R.nb_r[j][2]);
+      const float qxf = float(qx), qyf = float(qy), qzf = float(qz);
+      float ne, gx, gy, gz;
+      eval_grad<KIND>(a.g, R.nfg, R.te, C, O, bx, by, bz, ne, gx, gy, gz);
+      const float G1x = R.cf * gx, G1y = R.cf * gy, G1z = R.cf * gz;
+      float sjx = gx, sjy = gy, sjz = gz, tjx = gx, tjy = gy, tjz = gz;
+      eval_grad<KIND>(a.g, R.nfg, R.te, C, O, bx + hh * qxf, by + hh * qyf, bz + hh * qzf, ne, gx, gy, gz);
+      const float G2x = R.cf * gx, G2y = R.cf * gy, G2z = R.cf * gz;
+      sjx += gx; sjy += gy; sjz += gz;
+      tjx = fmaf(2.f, gx, tjx); tjy = fmaf(2.f, gy, tjy); tjz = fmaf(2.f, gz, tjz);
+      eval_grad<KIND>(a.g, R.nfg, R.te, C, O, bx + hh * (qxf + hh * G1x), by + hh * (qyf + hh * G1y),
+                      bz + hh * (qzf + hh * G1z), ne, gx, gy, gz);
+      sjx += gx; sjy += gy; sjz += gz;
+      tjx = fmaf(2.f, gx, tjx); tjy = fmaf(2.f, gy, tjy); tjz = fmaf(2.f, gz, tjz);
+      eval_grad<KIND>(a.g, R.nfg, R.te, C, O, bx + h * (qxf + hh * G2x), by + h * (qyf + hh * G2y),
+                      bz + h * (qzf + hh * G2z), ne, gx, gy, gz);
+      tjx += gx; tjy += gy; tjz += gz;
+      R.nb_r[j][0] += hd * R.nb_p[j][0] + hd * c6 * double(sjx - sx);
+      R.nb_r[j][1] += hd * R.nb_p[j][1] + hd * c6 * double(sjy - sy);
+      R.nb_r[j][2] += hd * R.nb_p[j][2] + hd * c6 * double(sjz - sz);
+      R.nb_p[j][0] += c6 * double(tjx - tx);
+      R.nb_p[j][1] += c6 * double(tjy - ty);
+      R.nb_p[j][2] += c6 * double(tjz - tz);
+    }
   }
   R.n += 1;
   if (!(isfinite(drx) && isfinite(dry) && isfinite(drz) && isfinite(dpx) && isfinite(dpy) && isfinite(dpz))) {
@@ -748,6 +825,17 @@ __device__ __forceinline__ int ray_step(const TraceArgs& a, RayState& R, CellCac
     // Eqs. 10-11: M = |(dr1 x dr2) . t| / eps^2; ln M from the accurately formed M - 1.
     const Real mm1 = fabs(det) * rcp_r(eps * eps) - Real(1);
     lnM = fast_log1pf(float(mm1));
+  }
+  if constexpr (carried) {
+    // cross-section of the carried tube at r_{i+1}: |(dr_a x dr_b) . p_hat|
+    const double* ua = R.nb_r[0];
+    const double* ub = R.nb_r[1];
+    const double cx = ua[1] * ub[2] - ua[2] * ub[1], cy = ua[2] * ub[0] - ua[0] * ub[2], cz = ua[0] * ub[1] - ua[1] * ub[0];
+    const double pp = R.px * R.px + R.py * R.py + R.pz * R.pz;
+    const double area = fabs(cx * R.px + cy * R.py + cz * R.pz) * rsqrt64(pp);
+    const double ln_s = log(area);
+    lnM = float(ln_s - R.tube_ln_s);
+    R.tube_ln_s = ln_s;
   }
 
   // Termination on the two spheres, last chord truncated at the crossing.

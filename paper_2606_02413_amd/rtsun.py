@@ -22,6 +22,7 @@ RT_USE_REFRACTION = 1 << 1
 RT_PREC_ALL_FP32 = 1 << 2
 RT_SCHED_PLAIN = 1 << 3
 RT_DETERMINISTIC_GRAD = 1 << 4
+RT_CARRIED_TUBE = 1 << 5
 RT_TEST_NO_ABSORPTION = 1 << 30
 
 EXIT_OUTER, HIT_INNER, MISS, MAX_STEPS, NONFINITE = 1, 2, 3, 4, 5
@@ -156,7 +157,7 @@ def image_desc(n, half_width, obs_dir=(1.0, 0.0, 0.0), up=(0.0, 0.0, 1.0), nv=No
 
 def params(*, ds_max=0.005, n_floor=1.0, max_steps=200000, eta=1e-2, tb_inner=1.0e4, tb_sky=0.0,
            refraction=True, magnification=True, all_fp32=False, plain=False, no_absorption=False,
-           checkpoint_every=64):
+           checkpoint_every=64, carried_tube=False):
     p = Params()
     lib().rt_params_default(C.byref(p))
     f = 0
@@ -165,6 +166,7 @@ def params(*, ds_max=0.005, n_floor=1.0, max_steps=200000, eta=1e-2, tb_inner=1.
     f |= RT_PREC_ALL_FP32 if all_fp32 else 0
     f |= RT_SCHED_PLAIN if plain else 0
     f |= RT_TEST_NO_ABSORPTION if no_absorption else 0
+    f |= RT_CARRIED_TUBE if carried_tube else 0
     p.flags = f
     p.ds_max, p.n_floor, p.max_steps = float(ds_max), float(n_floor), int(max_steps)
     p.perturb_ratio, p.tb_inner_K, p.tb_sky_K = float(eta), float(tb_inner), float(tb_sky)

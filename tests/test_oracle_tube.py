@@ -38,6 +38,12 @@ def test_carried_tube_in_a_quadratic_lens(h):
     # continuum: S / S_0 = cos^2(sqrt(beta) t) at the first step points
     t = h * np.arange(1, 6)
     assert np.max(np.abs(np.cumsum(path[:5, 4]) - 2 * np.log(np.abs(np.cos(math.sqrt(beta) * t))))) < 5 * h ** 4
+    # the smallest ln(S/S_0) over the step points (the last chord truncated at
+    # the sphere): the tube is squeezed towards the focus at sqrt(beta) t = pi/2
+    cum = np.cumsum(path[:, 4])
+    cum[-1] = cum[-2] + res["lam_last"] * path[-1, 4]
+    assert abs(res["ln_s_min"] - min(0.0, cum.min())) < 1e-9
+    assert res["ln_s_min"] < 2 * math.log(abs(math.cos(math.sqrt(beta) * h * (int(math.pi / 2 / math.sqrt(beta) / h))))) + 1e-6
 
 
 def test_carried_tube_is_constant_in_a_uniform_medium():
@@ -45,6 +51,7 @@ def test_carried_tube_is_constant_in_a_uniform_medium():
     P = O.make_params(ds_max=0.01, n_floor=0.1, carried_tube=True)
     res, path = O.trace_launch_path(med, P, 150e6, [2.9, 0.3, 0.2], [-1.0, 0.0, 0.0])
     assert np.max(np.abs(path[:, 4])) < 1e-12 and abs(res["ln_s_end"]) < 1e-10
+    assert -1e-10 < res["ln_s_min"] <= 0.0
 
 
 def test_carried_tube_converges_with_the_step_and_the_stepwise_area_does_not():
