@@ -43,7 +43,15 @@ VALU_PEAK_TFLOPS = 78.6
 # null as soon as those sources change.
 KERNEL_SOURCES = ("rt_trace.hpp", "rt_kernels.hip", "rt_internal.hpp")
 TRAFFIC = {"sources_sha256_16": "251b99832a2dbd14", "read_bytes": 2753048 * 1024 * 2.000,
-           "write_bytes": 17768 * 1024 * 1.000}
+           "write_bytes": 17768 * 1024 * 1.000,
+           # SQ_INSTS_VALU + 3 x SQ_INSTS_VALU_TRANS_F32 per ray-step (per lane) of
+           # the same profile: the VALU issue slots of the compiled step
+           "valu_slots_per_ray_step": 2708}
+# Model bytes one ray-step of this layout gathers (10 force evaluations x 8
+# corners x 16 B of (n_e, grad n_e) + one value evaluation x 8 x (4 B n_e + 4 B T)),
+# and the 448 B of a layout that stores n_e only and differentiates the corners.
+GATHER_BYTES_PER_RAY_STEP = 1344
+GATHER_BYTES_PER_RAY_STEP_NE_ONLY = 448
 
 
 def kernel_sources_hash():
@@ -641,6 +649,22 @@ def main():
                 "frac": round(achieved_tflops / VALU_PEAK_TFLOPS, 4), "traffic": traffic,
                 "kernel": "k_trace_persistent<mixed, spherical>", "flops_per_ray_step": FLOPS_PER_RAY_STEP,
                 "kernel_ms": round(ms_per_step, 3)}
+    # the other two rooflines of the tracer: VALU issue (from the profile's
+    # counters, for the same kernel sources) and the gathers against the
+    # measured streaming-read bandwidth of the L2 (probe kernel, this run)
+    valu = None
+    if kernel_sources_hash() == TRAFFIC["sources_sha256_16"]:
+        r_valu = 256 * 2.4e9 * 64 / TRAFFIC["valu_slots_per_ray_step"]
+        valu = {"slots_per_ray_step": TRAFFIC["valu_slots_per_ray_step"], "R_VALU_ray_steps_per_s": r_valu,
+                "frac": round(rate / r_valu, 4)}
+    bw = R.read_bandwidths(model.device)
+    r_l2 = bw["l2_GBps"] * 1e9 / GATHER_BYTES_PER_RAY_STEP
+    gathers = {"B_L2_GBps": round(bw["l2_GBps"], 1), "bytes_per_ray_step": GATHER_BYTES_PER_RAY_STEP,
+               "R_L2_ray_steps_per_s": r_l2, "frac": round(rate / r_l2, 4),
+               "frac_at_448_B_per_ray_step": round(rate / (bw["l2_GBps"] * 1e9 / GATHER_BYTES_PER_RAY_STEP_NE_ONLY), 4),
+               "gather_GBps_equivalent": round(rate * GATHER_BYTES_PER_RAY_STEP / 1e9, 1),
+               "infinity_cache_GBps": round(bw["infinity_cache_GBps"], 1), "hbm_GBps": round(bw["hbm_GBps"], 1)}
+    progress(f"rooflines: valu {valu}, gathers {gathers}")
     cpu = None if args.no_cpu else cpu_baseline(cor, wl, args.cpu_seconds)
     line = {
         "metric": "ray-steps/s and 512^2 x 8-freq T_b maps/s (plain vs batched); adjoint/fwd ratio",
@@ -667,6 +691,8 @@ def main():
         "adjoint": adjoint,
         "wall_s": wall,
         "roofline": roofline,
+        "valu_roofline": valu,
+        "l2_gather_roofline": gathers,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

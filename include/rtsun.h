@@ -291,6 +291,21 @@ rt_status rt_beam_convolve(const float* maps_in, float* maps_out, int32_t n_maps
 rt_status rt_disc_mean(const float* maps, int32_t n_maps, int32_t nu, int32_t nv, double half_u, double half_v,
                        double radius, double* mean_out, void* hip_stream);
 
+/* Measurement probe (not part of the method): the streaming read bandwidth
+ * that the tracer's gathers are compared with.  Allocates a device buffer of
+ * `bytes` on `device` (zero-filled; freed before return) and launches `blocks`
+ * 256-thread blocks, each reading `span_bytes` of it with float4 loads `reps`
+ * times: span_bytes = bytes makes every block read the whole buffer (from one
+ * die's L2 when bytes is at most its 4 MiB); span_bytes = bytes / blocks
+ * partitions it (from the 256 MB Infinity Cache or from HBM, by size).
+ * gbps_out: HOST double, bytes requested / kernel time (hipEvents around one
+ * launch after an untimed one) in GB/s.  Synchronises the stream.  Errors:
+ * RT_E_INVALID_ARG (bytes or span_bytes not a positive multiple of 16,
+ * span_bytes > bytes, blocks outside [1, 2^20], reps outside [1, 4096]),
+ * RT_E_OUT_OF_MEMORY, RT_E_DEVICE. */
+rt_status rt_probe_read_bandwidth(int32_t device, int64_t bytes, int64_t span_bytes, int32_t blocks, int32_t reps,
+                                  double* gbps_out, void* hip_stream);
+
 const char* rt_status_string(rt_status s);
 const char* rt_last_error_message(void);
 uint32_t rt_abi_version(void);

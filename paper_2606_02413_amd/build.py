@@ -7,7 +7,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB_PATH = os.path.join(HERE, "librtsun.so")
-SOURCES = ["rt_api.cpp", "rt_kernels.hip", "rt_adjoint.hip", "rt_maps.hip"]
+SOURCES = ["rt_api.cpp", "rt_kernels.hip", "rt_adjoint.hip", "rt_maps.hip", "rt_probe.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "rt_internal.hpp"
+#include "rt_probe.hpp"
 
 using namespace rt;
 
@@ -779,6 +780,53 @@ rt_status rt_disc_mean(const float* maps, int32_t n_maps, int32_t nu, int32_t nv
     d.pix_u = 2.0 * half_u / nu; d.pix_v = 2.0 * half_v / nv;
     d.radius2 = radius * radius;
     return hip_check(launch_disc_mean(d, maps, mean_out, static_cast<hipStream_t>(hip_stream)), "disc mean");
+  } catch (...) {
+    return fail(RT_E_INTERNAL, "unexpected exception");
+  }
+}
+
+rt_status rt_probe_read_bandwidth(int32_t device, int64_t bytes, int64_t span_bytes, int32_t blocks, int32_t reps,
+                                  double* gbps_out, void* hip_stream) {
+  try {
+    if (!gbps_out) return fail(RT_E_INVALID_ARG, "gbps_out is NULL");
+    if (bytes < 16 || bytes % 16 != 0) return fail(RT_E_INVALID_ARG, "bytes must be a positive multiple of 16");
+    if (span_bytes < 16 || span_bytes % 16 != 0 || span_bytes > bytes)
+      return fail(RT_E_INVALID_ARG, "span_bytes must be a multiple of 16 in [16, bytes]");
+    if (blocks < 1 || blocks > (1 << 20)) return fail(RT_E_INVALID_ARG, "blocks must be in [1, 2^20]");
+    if (reps < 1 || reps > 4096) return fail(RT_E_INVALID_ARG, "reps must be in [1, 4096]");
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    rt_status st = hip_check(hipSetDevice(device), "hipSetDevice");
+    if (st != RT_OK) return st;
+    float4* buf = nullptr;
+    float* sink = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    const size_t sink_bytes = size_t(blocks) * 256 * sizeof(float);
+    auto cleanup = [&]() {
+      if (e0) (void)hipEventDestroy(e0);
+      if (e1) (void)hipEventDestroy(e1);
+      dev_free(buf, size_t(bytes));
+      dev_free(sink, sink_bytes);
+    };
+    st = dev_alloc((void**)&buf, size_t(bytes), "probe buffer");
+    if (st == RT_OK) st = dev_alloc((void**)&sink, sink_bytes, "probe sink");
+    if (st == RT_OK) st = hip_check(hipMemsetAsync(buf, 0, size_t(bytes), s), "probe fill");
+    if (st == RT_OK) st = hip_check(hipEventCreate(&e0), "event");
+    if (st == RT_OK) st = hip_check(hipEventCreate(&e1), "event");
+    const long long n4 = bytes / 16, span4 = span_bytes / 16;
+    // one untimed launch, then the timed one
+    if (st == RT_OK) st = hip_check(launch_stream_read(buf, n4, span4, blocks, reps, sink, s), "probe launch");
+    if (st == RT_OK) st = hip_check(hipEventRecord(e0, s), "event record");
+    if (st == RT_OK) st = hip_check(launch_stream_read(buf, n4, span4, blocks, reps, sink, s), "probe launch");
+    if (st == RT_OK) st = hip_check(hipEventRecord(e1, s), "event record");
+    if (st == RT_OK) st = hip_check(hipEventSynchronize(e1), "event sync");
+    float ms = 0.f;
+    if (st == RT_OK) st = hip_check(hipEventElapsedTime(&ms, e0, e1), "elapsed");
+    if (st == RT_OK) {
+      if (!(ms > 0.f)) st = fail(RT_E_DEVICE, "probe time not positive");
+      else *gbps_out = double(span_bytes) * double(blocks) * double(reps) / (double(ms) * 1e-3) * 1e-9;
+    }
+    cleanup();
+    return st;
   } catch (...) {
     return fail(RT_E_INTERNAL, "unexpected exception");
   }

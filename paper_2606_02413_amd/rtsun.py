@@ -117,6 +117,9 @@ def lib():
         L.rt_beam_convolve.restype = C.c_int
         L.rt_disc_mean.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32, C.c_double, C.c_double, C.c_double, vp, vp]
         L.rt_disc_mean.restype = C.c_int
+        L.rt_probe_read_bandwidth.argtypes = [C.c_int32, C.c_int64, C.c_int64, C.c_int32, C.c_int32,
+                                              C.POINTER(C.c_double), vp]
+        L.rt_probe_read_bandwidth.restype = C.c_int
         _lib = L
     return _lib
 
@@ -359,6 +362,25 @@ def disc_mean(maps, image, radius=0.5, *, stream=None):
     _check(lib().rt_disc_mean(C.c_void_p(x.data_ptr()), n_maps, image.nu, image.nv, image.half_u, image.half_v,
                               float(radius), C.c_void_p(y.data_ptr()), _stream_ptr(stream)))
     return y.reshape(lead)
+
+
+def probe_read_bandwidth(device, nbytes, span_bytes, blocks, reps, *, stream=None):
+    """GB/s of the library's streaming-read probe (rt_probe_read_bandwidth)."""
+    out = C.c_double(0.0)
+    _check(lib().rt_probe_read_bandwidth(int(device), int(nbytes), int(span_bytes), int(blocks), int(reps),
+                                         C.byref(out), _stream_ptr(stream)))
+    return out.value
+
+
+def read_bandwidths(device=0, *, stream=None):
+    """Measured streaming-read bandwidths (GB/s) of one die's L2 (2 MiB read
+    whole by every block), the Infinity Cache (128 MiB partitioned) and HBM
+    (4 GiB partitioned), 2048 blocks of 256 threads."""
+    blocks = 2048
+    l2 = probe_read_bandwidth(device, 2 << 20, 2 << 20, blocks, 16, stream=stream)
+    mall = probe_read_bandwidth(device, 128 << 20, (128 << 20) // blocks, blocks, 64, stream=stream)
+    hbm = probe_read_bandwidth(device, 4 << 30, (4 << 30) // blocks, blocks, 4, stream=stream)
+    return {"l2_GBps": l2, "infinity_cache_GBps": mall, "hbm_GBps": hbm}
 
 
 def capture_trace_maps(models, freqs, image, prm, *, info=False, stats=True):

@@ -137,6 +137,18 @@ def test_map_postprocessing_validation(R):
     assert abs(R.beam_fwhm([40e6], 15e3)[0] - 0.1074) < 1e-3   # 7.49 m / 15 km = 5.0e-4 rad
 
 
+def test_read_probe_validation(R):
+    """The streaming-read probe rejects bad sizes before touching a device."""
+    L = R.lib()
+    out = C.c_double(0.0)
+    assert L.rt_probe_read_bandwidth(0, 1 << 20, 1 << 20, 64, 1, None, None) == 1
+    assert L.rt_probe_read_bandwidth(0, 0, 16, 64, 1, C.byref(out), None) == 1
+    assert L.rt_probe_read_bandwidth(0, 1000, 16, 64, 1, C.byref(out), None) == 1          # not a multiple of 16
+    assert L.rt_probe_read_bandwidth(0, 1 << 20, 2 << 20, 64, 1, C.byref(out), None) == 1  # span > bytes
+    assert L.rt_probe_read_bandwidth(0, 1 << 20, 1 << 20, 0, 1, C.byref(out), None) == 1
+    assert L.rt_probe_read_bandwidth(0, 1 << 20, 1 << 20, 64, 0, C.byref(out), None) == 1
+
+
 def test_binding_fails_loudly_without_library(R, monkeypatch):
     monkeypatch.setattr(R, "_lib", None)
     monkeypatch.setattr(R, "LIB_PATH", "/nonexistent/librtsun.so")
