@@ -664,6 +664,15 @@ def main():
                "frac_at_448_B_per_ray_step": round(rate / (bw["l2_GBps"] * 1e9 / GATHER_BYTES_PER_RAY_STEP_NE_ONLY), 4),
                "gather_GBps_equivalent": round(rate * GATHER_BYTES_PER_RAY_STEP / 1e9, 1),
                "infinity_cache_GBps": round(bw["infinity_cache_GBps"], 1), "hbm_GBps": round(bw["hbm_GBps"], 1)}
+    # gather-only replay of the same model's recorded walks (128^2 pixels x the 8
+    # frequencies): the rate the memory system serves this layout's gathers at
+    rep = R.gather_replay(model, wl.freqs, R.image_desc(128, wl.half_width),
+                          R.params(ds_max=wl.ds_max, n_floor=wl.n_floor, max_steps=wl.max_steps))
+    gathers["R_gather_ray_steps_per_s"] = rep["ray_steps_per_s"]
+    gathers["frac_of_R_gather"] = round(rate / rep["ray_steps_per_s"], 4)
+    gathers["replay"] = {"walks": rep["walks"], "capacity": rep["capacity"], "ray_steps": rep["ray_steps"],
+                         "ms": round(rep["ms"], 3)}
+    torch.cuda.empty_cache()
     progress(f"rooflines: valu {valu}, gathers {gathers}")
     cpu = None if args.no_cpu else cpu_baseline(cor, wl, args.cpu_seconds)
     line = {

@@ -306,6 +306,28 @@ rt_status rt_disc_mean(const float* maps, int32_t n_maps, int32_t nu, int32_t nv
 rt_status rt_probe_read_bandwidth(int32_t device, int64_t bytes, int64_t span_bytes, int32_t blocks, int32_t reps,
                                   double* gbps_out, void* hip_stream);
 
+/* Measurement probe: cell keys of recorded ray paths, the input of
+ * rt_probe_gather_replay.  path, path_len: DEVICE, as written by rt_trace_maps
+ * ([n_walks][path_capacity][9] float32 records, int32 lengths); keys_out: DEVICE
+ * int32 [path_capacity][n_walks], for record s of walk w the key
+ * (a n1 + b) n2p + c of the model cell holding its point (the tracer's cell
+ * clamping; n2p = n2 + 1 on spherical grids, n2 otherwise), -1 from the walk's
+ * length on.  Errors: RT_E_INVALID_ARG, RT_E_CAPACITY (n_walks x path_capacity
+ * above 2^31-1), RT_E_DEVICE. */
+rt_status rt_probe_path_keys(const rt_model* model, const float* path, const int32_t* path_len, int32_t n_walks,
+                             int32_t path_capacity, int32_t* keys_out, void* hip_stream);
+
+/* Measurement probe: gather-only replay of recorded cell walks with the model's
+ * layout and the tracer's per-lane cell cache (8 corners of float4 n_e/gradient
+ * and float T gathered into LDS when a walk's key changes, read back every
+ * step), one lane per walk, no ray arithmetic.  keys: DEVICE int32
+ * [path_capacity][n_walks] from rt_probe_path_keys (a key < 0 or beyond the
+ * grid ends the walk).  ms_out: HOST double, kernel time of one launch after
+ * an untimed one (hipEvents).  Synchronises the stream.  Errors:
+ * RT_E_INVALID_ARG, RT_E_CAPACITY, RT_E_OUT_OF_MEMORY, RT_E_DEVICE. */
+rt_status rt_probe_gather_replay(const rt_model* model, const int32_t* keys, int32_t n_walks, int32_t path_capacity,
+                                 double* ms_out, void* hip_stream);
+
 const char* rt_status_string(rt_status s);
 const char* rt_last_error_message(void);
 uint32_t rt_abi_version(void);

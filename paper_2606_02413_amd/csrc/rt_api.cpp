@@ -832,6 +832,67 @@ rt_status rt_probe_read_bandwidth(int32_t device, int64_t bytes, int64_t span_by
   }
 }
 
+rt_status rt_probe_path_keys(const rt_model* model, const float* path, const int32_t* path_len, int32_t n_walks,
+                             int32_t path_capacity, int32_t* keys_out, void* hip_stream) {
+  try {
+    if (!model || !path || !path_len || !keys_out) return fail(RT_E_INVALID_ARG, "NULL argument");
+    if (n_walks < 1 || path_capacity < 1) return fail(RT_E_INVALID_ARG, "n_walks and path_capacity must be >= 1");
+    if ((long long)n_walks * path_capacity > (1ll << 31) - 1) return fail(RT_E_CAPACITY, "more than 2^31-1 keys");
+    rt_status st = hip_check(hipSetDevice(model->device), "hipSetDevice");
+    if (st != RT_OK) return st;
+    return hip_check(launch_path_keys(model->geom, path, path_len, n_walks, path_capacity, keys_out,
+                                      static_cast<hipStream_t>(hip_stream)),
+                     "path keys");
+  } catch (...) {
+    return fail(RT_E_INTERNAL, "unexpected exception");
+  }
+}
+
+rt_status rt_probe_gather_replay(const rt_model* model, const int32_t* keys, int32_t n_walks, int32_t path_capacity,
+                                 double* ms_out, void* hip_stream) {
+  try {
+    if (!model || !keys || !ms_out) return fail(RT_E_INVALID_ARG, "NULL argument");
+    if (n_walks < 1 || path_capacity < 1) return fail(RT_E_INVALID_ARG, "n_walks and path_capacity must be >= 1");
+    if ((long long)n_walks * path_capacity > (1ll << 31) - 1) return fail(RT_E_CAPACITY, "more than 2^31-1 keys");
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    rt_status st = hip_check(hipSetDevice(model->device), "hipSetDevice");
+    if (st != RT_OK) return st;
+    const DevGeom& g = model->geom;
+    const int s1 = g.n2p, s0 = g.n1 * g.n2p;
+    const long long n_vert = (long long)g.n0 * s0;
+    const long long mk = n_vert - 1 - (s0 + s1 + 1);
+    if (mk < 0) return fail(RT_E_INVALID_ARG, "grid too small");
+    const int max_key = int(std::min<long long>(mk, (1ll << 31) - 1));
+    float* sink = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    const size_t sink_bytes = size_t(n_walks) * sizeof(float);
+    auto cleanup = [&]() {
+      if (e0) (void)hipEventDestroy(e0);
+      if (e1) (void)hipEventDestroy(e1);
+      dev_free(sink, sink_bytes);
+    };
+    st = dev_alloc((void**)&sink, sink_bytes, "replay sink");
+    if (st == RT_OK) st = hip_check(hipEventCreate(&e0), "event");
+    if (st == RT_OK) st = hip_check(hipEventCreate(&e1), "event");
+    auto launch = [&]() {
+      return hip_check(launch_gather_replay(model->nfg, model->te, keys, n_walks, path_capacity, s0, s1, max_key, sink, s),
+                       "replay launch");
+    };
+    if (st == RT_OK) st = launch();
+    if (st == RT_OK) st = hip_check(hipEventRecord(e0, s), "event record");
+    if (st == RT_OK) st = launch();
+    if (st == RT_OK) st = hip_check(hipEventRecord(e1, s), "event record");
+    if (st == RT_OK) st = hip_check(hipEventSynchronize(e1), "event sync");
+    float ms = 0.f;
+    if (st == RT_OK) st = hip_check(hipEventElapsedTime(&ms, e0, e1), "elapsed");
+    if (st == RT_OK) *ms_out = double(ms);
+    cleanup();
+    return st;
+  } catch (...) {
+    return fail(RT_E_INTERNAL, "unexpected exception");
+  }
+}
+
 rt_status rt_trace_adjoint(const rt_model* model, const double* freq_hz, int32_t n_freq, const rt_image_desc* image,
                            const rt_params* params, const float* weights, double* loss_out, float* grad_ln_ne,
                            float* grad_ln_te, float* tb_out, void* hip_stream) {

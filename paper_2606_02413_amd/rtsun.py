@@ -120,6 +120,10 @@ def lib():
         L.rt_probe_read_bandwidth.argtypes = [C.c_int32, C.c_int64, C.c_int64, C.c_int32, C.c_int32,
                                               C.POINTER(C.c_double), vp]
         L.rt_probe_read_bandwidth.restype = C.c_int
+        L.rt_probe_path_keys.argtypes = [vp, vp, vp, C.c_int32, C.c_int32, vp, vp]
+        L.rt_probe_path_keys.restype = C.c_int
+        L.rt_probe_gather_replay.argtypes = [vp, vp, C.c_int32, C.c_int32, C.POINTER(C.c_double), vp]
+        L.rt_probe_gather_replay.restype = C.c_int
         _lib = L
     return _lib
 
@@ -381,6 +385,32 @@ def read_bandwidths(device=0, *, stream=None):
     mall = probe_read_bandwidth(device, 128 << 20, (128 << 20) // blocks, blocks, 64, stream=stream)
     hbm = probe_read_bandwidth(device, 4 << 30, (4 << 30) // blocks, blocks, 4, stream=stream)
     return {"l2_GBps": l2, "infinity_cache_GBps": mall, "hbm_GBps": hbm}
+
+
+def gather_replay(model, freqs, image, prm, *, max_bytes=40 << 30, stream=None):
+    """Gather-only replay of one trace_maps call's walks (rt_probe_path_keys,
+    rt_probe_gather_replay): every ray of the call is recorded (capacity = the
+    longest ray, capped so the records fit in max_bytes), its points turned into
+    cell keys, and the replay of all walks timed.  Returns a dict with the
+    replayed ray-steps, the replay time and their ratio."""
+    import torch
+    first = trace_maps([model], freqs, image, prm, info=True, stats=False, stream=stream)
+    n_rays = first["tb"].numel()
+    n_steps = decode_info(first["info"])["n_steps"].reshape(-1)
+    cap = int(max(1, min(int(n_steps.max()), max_bytes // (n_rays * 9 * 4))))
+    rec = trace_maps([model], freqs, image, prm, info=False, stats=False, stream=stream,
+                     path_rays=np.arange(n_rays, dtype=np.int32), path_capacity=cap)
+    keys = torch.empty((cap, n_rays), dtype=torch.int32, device=rec["tb"].device)
+    _check(lib().rt_probe_path_keys(model.handle, C.c_void_p(rec["path"].data_ptr()),
+                                    C.c_void_p(rec["path_len"].data_ptr()), n_rays, cap,
+                                    C.c_void_p(keys.data_ptr()), _stream_ptr(stream)))
+    steps = int(rec["path_len"].sum().item())
+    del rec
+    ms = C.c_double(0.0)
+    _check(lib().rt_probe_gather_replay(model.handle, C.c_void_p(keys.data_ptr()), n_rays, cap, C.byref(ms),
+                                        _stream_ptr(stream)))
+    return {"walks": n_rays, "capacity": cap, "ray_steps": steps, "ms": ms.value,
+            "ray_steps_per_s": steps / (ms.value * 1e-3)}
 
 
 def capture_trace_maps(models, freqs, image, prm, *, info=False, stats=True):

@@ -147,6 +147,9 @@ def test_read_probe_validation(R):
     assert L.rt_probe_read_bandwidth(0, 1 << 20, 2 << 20, 64, 1, C.byref(out), None) == 1  # span > bytes
     assert L.rt_probe_read_bandwidth(0, 1 << 20, 1 << 20, 0, 1, C.byref(out), None) == 1
     assert L.rt_probe_read_bandwidth(0, 1 << 20, 1 << 20, 64, 0, C.byref(out), None) == 1
+    buf = C.c_void_p(16)
+    assert L.rt_probe_path_keys(None, buf, buf, 4, 4, buf, None) == 1
+    assert L.rt_probe_gather_replay(None, buf, 4, 4, C.byref(out), None) == 1
 
 
 def test_binding_fails_loudly_without_library(R, monkeypatch):
