@@ -393,8 +393,8 @@ struct AdjState {
 // The tracing mode is a compile-time choice (kModeLos, kModeNoMag, kModeFull);
 // absorption is always on.
 template <int KIND, int MODE>
-__device__ __forceinline__ void step_adjoint(const AdjointArgs& aa, const RayState& R, const float* tp, size_t ts, CellCache& C,
-                             GradAcc& A, float* lg, int code, double wgt, AdjState& S) {
+__device__ __forceinline__ void step_adjoint(const AdjointArgs& aa, const RayState& R, const float (&tv)[kTapeFields],
+                                             CellCache& C, GradAcc& A, float* lg, int code, double wgt, AdjState& S) {
   static_assert(MODE == kModeLos || MODE == kModeNoMag || MODE == kModeFull, "fixed tracing mode");
   const TraceArgs& a = aa.t;
   const DevGeom& g = a.g;
@@ -415,15 +415,15 @@ __device__ __forceinline__ void step_adjoint(const AdjointArgs& aa, const RaySta
   float ni = 0.f;
   bool floored = true;
   if constexpr (refr) {
-    ni = tp[kTapeNi * ts];
+    ni = tv[kTapeNi];
     floored = !(ni > a.n_floor);
     hd = floored ? a.ds_max_d * rcp64(a.n_floor_d) : a.ds_max_d * rcp64(double(ni));
     h = float(hd);
     hh = 0.5f * h;
     hq = hh * hh;
-    F1x = tp[kTapeF1 * ts]; F1y = tp[(kTapeF1 + 1) * ts]; F1z = tp[(kTapeF1 + 2) * ts];
-    F2x = tp[kTapeF2 * ts]; F2y = tp[(kTapeF2 + 1) * ts]; F2z = tp[(kTapeF2 + 2) * ts];
-    sx = tp[kTapeS * ts]; sy = tp[(kTapeS + 1) * ts]; sz = tp[(kTapeS + 2) * ts];
+    F1x = tv[kTapeF1]; F1y = tv[kTapeF1 + 1]; F1z = tv[kTapeF1 + 2];
+    F2x = tv[kTapeF2]; F2y = tv[kTapeF2 + 1]; F2z = tv[kTapeF2 + 2];
+    sx = tv[kTapeS]; sy = tv[kTapeS + 1]; sz = tv[kTapeS + 2];
     d2x = hh * pxf; d2y = hh * pyf; d2z = hh * pzf;
     d3x = hh * (pxf + hh * F1x); d3y = hh * (pyf + hh * F1y); d3z = hh * (pzf + hh * F1z);
     const double c6 = R.cfd * hd * (1.0 / 6.0);
@@ -457,12 +457,12 @@ __device__ __forceinline__ void step_adjoint(const AdjointArgs& aa, const RaySta
     e2x = uy * e1z - uz * e1y; e2y = uz * e1x - ux * e1z; e2z = ux * e1y - uy * e1x;
     eps = double(a.eta) * ds;
     // s_j = eps e_j + h^2/6 a_j, a_j the force-difference sums of the record
-    s1x = eps * e1x + double(hh6 * tp[kTapeA * ts]);
-    s1y = eps * e1y + double(hh6 * tp[(kTapeA + 1) * ts]);
-    s1z = eps * e1z + double(hh6 * tp[(kTapeA + 2) * ts]);
-    s2x = eps * e2x + double(hh6 * tp[(kTapeA + 3) * ts]);
-    s2y = eps * e2y + double(hh6 * tp[(kTapeA + 4) * ts]);
-    s2z = eps * e2z + double(hh6 * tp[(kTapeA + 5) * ts]);
+    s1x = eps * e1x + double(hh6 * tv[kTapeA]);
+    s1y = eps * e1y + double(hh6 * tv[kTapeA + 1]);
+    s1z = eps * e1z + double(hh6 * tv[kTapeA + 2]);
+    s2x = eps * e2x + double(hh6 * tv[kTapeA + 3]);
+    s2y = eps * e2y + double(hh6 * tv[kTapeA + 4]);
+    s2z = eps * e2z + double(hh6 * tv[kTapeA + 5]);
     det = (s1y * s2z - s1z * s2y) * ux + (s1z * s2x - s1x * s2z) * uy + (s1x * s2y - s1y * s2x) * uz;
     const double mm1 = fabs(det) * rcp64(eps * eps) - 1.0;
     lnM = fast_log1pf(float(mm1));
@@ -474,7 +474,7 @@ __device__ __forceinline__ void step_adjoint(const AdjointArgs& aa, const RaySta
   else if (code == kExit) lam = crossing<double>(R.rx, R.ry, R.rz, drx, dry, drz, g.r_max, true);
   const float hl = 0.5f * float(lam);
   const float mdx = hl * float(drx), mdy = hl * float(dry), mdz = hl * float(drz);
-  const float ne_m = tp[kTapeNeM * ts], te_m = tp[kTapeTeM * ts];
+  const float ne_m = tv[kTapeNeM], te_m = tv[kTapeTeM];
   float kn, lnl, cl;
   double dtau;
   {
@@ -551,10 +551,10 @@ __device__ __forceinline__ void step_adjoint(const AdjointArgs& aa, const RaySta
     for (int jj = 0; jj < 2; ++jj) {
       const double ex_ = jj ? e2x : e1x, ey_ = jj ? e2y : e1y, ez_ = jj ? e2z : e1z;
       const double sbx = jj ? sb2x : sb1x, sby = jj ? sb2y : sb1y, sbz = jj ? sb2z : sb1z;
-      const float* aj = tp + size_t(kTapeA + 3 * jj) * ts;
-      const float* qj = tp + size_t(kTapeQ + 3 * jj) * ts;
-      const float ajx = aj[0], ajy = aj[ts], ajz = aj[2 * ts];
-      const float qjx = qj[0], qjy = qj[ts], qjz = qj[2 * ts];
+      const float ajx = jj ? tv[kTapeA + 3] : tv[kTapeA], ajy = jj ? tv[kTapeA + 4] : tv[kTapeA + 1],
+                  ajz = jj ? tv[kTapeA + 5] : tv[kTapeA + 2];
+      const float qjx = jj ? tv[kTapeQ + 3] : tv[kTapeQ], qjy = jj ? tv[kTapeQ + 4] : tv[kTapeQ + 1],
+                  qjz = jj ? tv[kTapeQ + 5] : tv[kTapeQ + 2];
       const float fx = float(eps * ex_), fy = float(eps * ey_), fz = float(eps * ez_);
       // s_j = eps e_j + h^2/6 a_j
       eps_b += sbx * ex_ + sby * ey_ + sbz * ez_;
@@ -624,8 +624,8 @@ __device__ __forceinline__ void step_adjoint(const AdjointArgs& aa, const RaySta
     pbx += hd * drbx; pby += hd * drby; pbz += hd * drbz;
     const double ks = hd * hd * (1.0 / 6.0) * R.cfd;
     const float sbx = float(ks * drbx), sby = float(ks * drby), sbz = float(ks * drbz);
-    hd_b += (R.cfd / 6.0) * (dpbx * double(tp[kTapeT * ts]) + dpby * double(tp[(kTapeT + 1) * ts]) +
-                             dpbz * double(tp[(kTapeT + 2) * ts]));
+    hd_b += (R.cfd / 6.0) * (dpbx * double(tv[kTapeT]) + dpby * double(tv[kTapeT + 1]) +
+                             dpbz * double(tv[kTapeT + 2]));
     const double kt = hd * (1.0 / 6.0) * R.cfd;
     const float tbx_ = float(kt * dpbx), tby_ = float(kt * dpby), tbz_ = float(kt * dpbz);
     g1bx += sbx + tbx_; g1by += sby + tby_; g1bz += sbz + tbz_;
@@ -707,6 +707,18 @@ __device__ __forceinline__ void state_load(const double* buf, int entry, int lim
 // Record of chunk step `entry` (0 <= entry < K, which the chunk loop keeps).
 __device__ __forceinline__ float* tape_entry(const AdjointArgs& aa, int entry, int slot) {
   return aa.tape + size_t(entry) * kTapeFields * size_t(aa.n_slots) + slot;
+}
+
+// The fields of a step's record that the mode's backward step reads, all
+// loaded at once (one memory round trip per step instead of one per use).
+template <int MODE>
+__device__ __forceinline__ void tape_read(const float* tp, size_t ts, float (&tv)[kTapeFields]) {
+#pragma unroll
+  for (int f = 0; f < kTapeFields; ++f) {
+    const bool used = (f == kTapeNeM || f == kTapeTeM) || (MODE != kModeLos && f < kTapeQ) ||
+                      (MODE == kModeFull && f >= kTapeQ && f < kTapeNeM);
+    tv[f] = used ? tp[size_t(f) * ts] : 0.0f;
+  }
 }
 
 __device__ __forceinline__ void state_copy(double* buf, int from, int to, int limit, int n_slots, int slot) {
@@ -797,9 +809,10 @@ __device__ __forceinline__ void adjoint_reverse_ray(const AdjointArgs& aa, int i
       }
       for (int i = c1 - 1; i >= c0; --i) {
         state_load(aa.steps, i - c0, aa.K, aa.n_slots, slot, R);
+        float tv[kTapeFields];
+        tape_read<MODE>(tape_entry(aa, i - c0, slot), ts, tv);
         R.n = i;
-        step_adjoint<KIND, MODE>(aa, R, tape_entry(aa, i - c0, slot), ts, C, A, lg, (i == N - 1) ? code : kRunning,
-                                 wgt, S);
+        step_adjoint<KIND, MODE>(aa, R, tv, C, A, lg, (i == N - 1) ? code : kRunning, wgt, S);
       }
     }
   }
