@@ -390,6 +390,9 @@ struct AdjState {
 // step's derived quantities are recomputed from these with ray_step's
 // arithmetic.  S holds the adjoint of the state after the step and the
 // brightness behind it, and is replaced by the adjoint of the start state.  `code` is the termination code the forward step returned.
+// The evaluation log entries of the central stages (or of the midpoint, on a
+// straight line of sight) are left in the log for step_adjoint_flush, so that
+// the caller can issue the next step's loads before that replay's atomics.
 // The tracing mode is a compile-time choice (kModeLos, kModeNoMag, kModeFull);
 // absorption is always on.
 template <int KIND, int MODE>
@@ -668,13 +671,21 @@ __device__ __forceinline__ void step_adjoint(const AdjointArgs& aa, const RaySta
     // first stage at r_i (gradient and the value that set the step)
     eval_grad_adj<KIND, true>(g, R, C, lg, e0 + 3, O, 0.f, 0.f, 0.f, g1bx, g1by, g1bz, ne1_b, qx, qy, qz);
     rbx += qx; rby += qy; rbz += qz;
-    log_replay<!mag, true>(g, A, gacc, lg, e0 + 4);
   } else {
     pbx += hd * drbx; pby += hd * drby; pbz += hd * drbz;
-    log_replay<true, false>(g, A, gacc, lg, 1);
   }
   S.rbx = rbx; S.rby = rby; S.rbz = rbz;
   S.pbx = pbx; S.pby = pby; S.pbz = pbz;
+}
+
+// Replay of the log entries step_adjoint leaves: the central stages (after the
+// midpoint value when the perturbed retraces' replay has not taken it), or the
+// midpoint alone on a straight line of sight.
+template <int MODE>
+__device__ __forceinline__ void step_adjoint_flush(const DevGeom& g, GradAcc& A, double* gacc, float* lg) {
+  if constexpr (MODE == kModeFull) log_replay<false, true>(g, A, gacc, lg, 4);
+  else if constexpr (MODE == kModeNoMag) log_replay<true, true>(g, A, gacc, lg, 5);
+  else log_replay<true, false>(g, A, gacc, lg, 1);
 }
 
 // ---------------------------------------------------------------------------
@@ -807,12 +818,19 @@ __device__ __forceinline__ void adjoint_reverse_ray(const AdjointArgs& aa, int i
         }
         ray_step<true, KIND, MODE, true>(a, R, C, tp, ts);
       }
+      // the next (earlier) step's state and record are loaded before the
+      // replay of this step's last log entries issues its atomics
+      float tv[kTapeFields];
+      state_load(aa.steps, c1 - 1 - c0, aa.K, aa.n_slots, slot, R);
+      tape_read<MODE>(tape_entry(aa, c1 - 1 - c0, slot), ts, tv);
       for (int i = c1 - 1; i >= c0; --i) {
-        state_load(aa.steps, i - c0, aa.K, aa.n_slots, slot, R);
-        float tv[kTapeFields];
-        tape_read<MODE>(tape_entry(aa, i - c0, slot), ts, tv);
         R.n = i;
         step_adjoint<KIND, MODE>(aa, R, tv, C, A, lg, (i == N - 1) ? code : kRunning, wgt, S);
+        if (i > c0) {
+          state_load(aa.steps, i - 1 - c0, aa.K, aa.n_slots, slot, R);
+          tape_read<MODE>(tape_entry(aa, i - 1 - c0, slot), ts, tv);
+        }
+        step_adjoint_flush<MODE>(a.g, A, aa.gacc, lg);
       }
     }
   }
