@@ -42,8 +42,8 @@ VALU_PEAK_TFLOPS = 78.6
 # valid only for the kernel sources they were taken on (hash below); reported as
 # null as soon as those sources change.
 KERNEL_SOURCES = ("rt_trace.hpp", "rt_kernels.hip", "rt_internal.hpp")
-TRAFFIC = {"sources_sha256_16": "251b99832a2dbd14", "read_bytes": 2753048 * 1024 * 2.000,
-           "write_bytes": 17768 * 1024 * 1.000,
+TRAFFIC = {"sources_sha256_16": "251b99832a2dbd14", "read_bytes": 2787903 * 1024 * 2.000,
+           "write_bytes": 18039 * 1024 * 1.000,
            # SQ_INSTS_VALU + 3 x SQ_INSTS_VALU_TRANS_F32 per ray-step (per lane) of
            # the same profile: the VALU issue slots of the compiled step
            "valu_slots_per_ray_step": 2708}
@@ -71,6 +71,8 @@ def parse():
     ap.add_argument("--no-plain", action="store_true", help="skip the plain per-frequency timing")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint / forward timing")
+    ap.add_argument("--no-probe", action="store_true",
+                    help="skip the read-bandwidth probe and the gather replay (for profiling the tracer alone)")
     ap.add_argument("--autotune-freqs", type=int, default=4,
                     help="frequencies in the autotuner's sample of the workload (0: no autotuning, defaults)")
     ap.add_argument("--tuning", default=None,
@@ -533,6 +535,30 @@ def batching_study():
     mdl.close()
 
 
+def l2_gather_roofline(R, torch, model, wl, rate):
+    """The L2-gather roofline of the tracer: R_L2 from the measured streaming
+    read bandwidth of the L2 and the layout's gathered bytes per ray-step, and
+    R_gather from the gather-only replay of the model's recorded walks."""
+    bw = R.read_bandwidths(model.device)
+    r_l2 = bw["l2_GBps"] * 1e9 / GATHER_BYTES_PER_RAY_STEP
+    gathers = {"B_L2_GBps": round(bw["l2_GBps"], 1), "bytes_per_ray_step": GATHER_BYTES_PER_RAY_STEP,
+               "R_L2_ray_steps_per_s": r_l2, "frac": round(rate / r_l2, 4),
+               "frac_at_448_B_per_ray_step": round(rate / (bw["l2_GBps"] * 1e9 / GATHER_BYTES_PER_RAY_STEP_NE_ONLY), 4),
+               "gather_GBps_equivalent": round(rate * GATHER_BYTES_PER_RAY_STEP / 1e9, 1),
+               "infinity_cache_GBps": round(bw["infinity_cache_GBps"], 1), "hbm_GBps": round(bw["hbm_GBps"], 1)}
+    # gather-only replay of the same model's recorded walks (128^2 pixels x the 8
+    # frequencies): the rate the memory system serves this layout's gathers at
+    rep = R.gather_replay(model, wl.freqs, R.image_desc(128, wl.half_width),
+                          R.params(ds_max=wl.ds_max, n_floor=wl.n_floor, max_steps=wl.max_steps))
+    gathers["R_gather_ray_steps_per_s"] = rep["ray_steps_per_s"]
+    gathers["frac_of_R_gather"] = round(rate / rep["ray_steps_per_s"], 4)
+    gathers["replay"] = {"walks": rep["walks"], "capacity": rep["capacity"], "ray_steps": rep["ray_steps"],
+                         "ms": round(rep["ms"], 3)}
+    torch.cuda.empty_cache()
+    progress(f"l2-gather roofline: {gathers}")
+    return gathers
+
+
 def main():
     args = parse()
     if args.calibrate_copy:
@@ -657,23 +683,7 @@ def main():
         r_valu = 256 * 2.4e9 * 64 / TRAFFIC["valu_slots_per_ray_step"]
         valu = {"slots_per_ray_step": TRAFFIC["valu_slots_per_ray_step"], "R_VALU_ray_steps_per_s": r_valu,
                 "frac": round(rate / r_valu, 4)}
-    bw = R.read_bandwidths(model.device)
-    r_l2 = bw["l2_GBps"] * 1e9 / GATHER_BYTES_PER_RAY_STEP
-    gathers = {"B_L2_GBps": round(bw["l2_GBps"], 1), "bytes_per_ray_step": GATHER_BYTES_PER_RAY_STEP,
-               "R_L2_ray_steps_per_s": r_l2, "frac": round(rate / r_l2, 4),
-               "frac_at_448_B_per_ray_step": round(rate / (bw["l2_GBps"] * 1e9 / GATHER_BYTES_PER_RAY_STEP_NE_ONLY), 4),
-               "gather_GBps_equivalent": round(rate * GATHER_BYTES_PER_RAY_STEP / 1e9, 1),
-               "infinity_cache_GBps": round(bw["infinity_cache_GBps"], 1), "hbm_GBps": round(bw["hbm_GBps"], 1)}
-    # gather-only replay of the same model's recorded walks (128^2 pixels x the 8
-    # frequencies): the rate the memory system serves this layout's gathers at
-    rep = R.gather_replay(model, wl.freqs, R.image_desc(128, wl.half_width),
-                          R.params(ds_max=wl.ds_max, n_floor=wl.n_floor, max_steps=wl.max_steps))
-    gathers["R_gather_ray_steps_per_s"] = rep["ray_steps_per_s"]
-    gathers["frac_of_R_gather"] = round(rate / rep["ray_steps_per_s"], 4)
-    gathers["replay"] = {"walks": rep["walks"], "capacity": rep["capacity"], "ray_steps": rep["ray_steps"],
-                         "ms": round(rep["ms"], 3)}
-    torch.cuda.empty_cache()
-    progress(f"rooflines: valu {valu}, gathers {gathers}")
+    gathers = None if args.no_probe else l2_gather_roofline(R, torch, model, wl, rate)
     cpu = None if args.no_cpu else cpu_baseline(cor, wl, args.cpu_seconds)
     line = {
         "metric": "ray-steps/s and 512^2 x 8-freq T_b maps/s (plain vs batched); adjoint/fwd ratio",
