@@ -22,6 +22,10 @@
 //     Per segment the exact solution for constant kappa, T and d ln S/ds is used.
 //   * Thermal free-free absorption in its Rayleigh-Jeans closed form with the
 //     two-branch Coulomb logarithm (Dulk 1985, ARA&A 23, 169, cited in Sec. 1).
+//   * Optionally (carried_tube) the tube cross-section S of Eqs. 2-3 from two
+//     neighbour rays launched once across the initial direction and stepped
+//     beside the ray for its whole length, ln M of a step = ln(S_{i+1}/S_i);
+//     each ray also reports the smallest ln(S/S_0) over its step points.
 //
 // A second stepper (Dormand-Prince 5(4) with error control) traces the central
 // ray only; it is the physics reference for invariants, not for parity.
