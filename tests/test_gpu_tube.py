@@ -154,3 +154,48 @@ def test_carried_tube_rejected_combinations(R, structured_small):
     with pytest.raises(R.RtError) as e:
         R.autotune([m], [60e6], im, R.params(carried_tube=True))
     assert e.value.status == 1
+
+
+def test_carried_tube_cartesian_slab(R, orc):
+    """Linear slab on a Cartesian grid (constant force: the neighbours separate
+    only through their launch wavevectors): carried tube parity."""
+    n = 25
+    k = np.arange(n)
+    ne = np.broadcast_to((1e6 + 5e4 * k)[None, None, :], (n, n, n)).astype(np.float32).copy()
+    te = np.full((n, n, n), 1e6, np.float32)
+    d = R.grid_desc(R.RT_GRID_CARTESIAN, (n, n, n), -1.0, 5.0, origin=(-6, -6, -6), spacing=(0.5, 0.5, 0.5))
+    m = R.Model(d, ne, te)
+    kw = dict(PU.step_kwargs(0.01, 1.0), carried_tube=True)
+    print("case carried cartesian", flush=True)
+    g = PU.gpu_trace([m], [20e6], 16, 3.0, kw)
+    med = orc.OracleMedium(orc.GRID_CARTESIAN, shape=(n, n, n), r_in=-1.0, r_max=5.0, ne=ne, te=te,
+                           origin=(-6, -6, -6), spacing=(0.5, 0.5, 0.5))
+    o = orc.trace_pixels(med, orc.make_params(**kw), orc.make_image(16, 3.0), 20e6, np.arange(256, dtype=np.int32))
+    info = g["info"].reshape(-1)
+    PU.compare(g["tb"].reshape(-1), info, o, label="carried-cartesian")
+    _carried(info, o)
+    m.close()
+
+
+def test_carried_tube_path_records(R, orc):
+    """Per-step ln M of the carried tube in the path records, summed along the
+    ray, follows the oracle's ln(S_i / S_0) at every step point."""
+    cor = corona.spherically_symmetric()
+    m = R.Model.from_corona(cor)
+    kw = dict(PU.step_kwargs(0.005, 1.0), carried_tube=True)
+    rays = [10 * 64 + 12, 32 * 64 + 30]
+    print("case carried paths", flush=True)
+    g = PU.gpu_trace([m], [80e6], 64, 2.5, kw, path_rays=rays, path_capacity=2000)
+    med = orc.OracleMedium.from_corona(cor)
+    for slot, ray in enumerate(sorted(rays)):
+        res, path = orc.trace_pixel_path(med, orc.make_params(**kw), orc.make_image(64, 2.5), 80e6, ray)
+        n = int(g["path_len"][slot])
+        assert n == len(path) == res["n_steps"]
+        cg = np.cumsum(g["path"][slot, :n, 4].astype(np.float64))
+        co = np.cumsum(path[:, 4])
+        bound = (LN_S_ABS_TOL + LN_S_REL_TOL * np.abs(co)
+                 + LN_S_SQUEEZE_TOL * (np.exp(-0.5 * res["ln_s_min"]) - 1.0))
+        print("carried path", ray, "max |d ln S_i|", float(np.abs(cg - co).max()), "ln S_min", float(res["ln_s_min"]),
+              flush=True)
+        assert np.all(np.abs(cg - co) <= bound)
+    m.close()
