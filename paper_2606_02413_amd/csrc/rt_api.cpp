@@ -538,7 +538,7 @@ rt_status rt_trace_maps(const rt_model* const* models, int32_t n_models, const d
       }
       st = hip_check(launch_fill_u32(a.counters, 0u, kXcds, s), "counter fill");
       if (st != RT_OK) return st;
-      int per_cu = persistent_blocks_per_cu(mixed, a.g.kind);
+      int per_cu = persistent_blocks_per_cu(mixed, a.g.kind, P.flags);
       if (tune.blocks_per_cu > 0 && tune.blocks_per_cu < per_cu) per_cu = tune.blocks_per_cu;
       long long blocks = (long long)sc->n_cu * per_cu;
       const long long max_useful = ((long long)a.range_lo[kXcds] + 3) / 4;
@@ -641,7 +641,7 @@ rt_status rt_autotune(const rt_model* const* models, int32_t n_models, const dou
     if (st == RT_OK) st = hip_check(hipEventCreate(&e1), "event");
     if (st != RT_OK) { cleanup(); return st; }
     const bool mixed = (params->flags & RT_PREC_ALL_FP32) == 0;
-    const int max_per_cu = persistent_blocks_per_cu(mixed, models[0]->geom.kind);
+    const int max_per_cu = persistent_blocks_per_cu(mixed, models[0]->geom.kind, params->flags);
     std::vector<rt_tuning> cand;
     rt_tuning d;
     rt_tuning_default(&d);

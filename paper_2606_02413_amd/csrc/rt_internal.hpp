@@ -114,7 +114,7 @@ hipError_t launch_fill_u32(unsigned* p, unsigned val, long long n, hipStream_t s
 hipError_t launch_count_diff(const unsigned* a, const unsigned* b, long long n, unsigned* count, hipStream_t s);
 hipError_t launch_trace(const TraceArgs& a, bool plain, bool mixed, int grid_blocks, hipStream_t s);
 hipError_t launch_start_index(const TraceArgs& a, double* out, float* ne_out, hipStream_t s);
-int persistent_blocks_per_cu(bool mixed, int kind);
+int persistent_blocks_per_cu(bool mixed, int kind, uint32_t flags);
 
 // Launchers (rt_adjoint.hip).
 hipError_t launch_adjoint_forward(const AdjointArgs& a, hipStream_t s);

@@ -214,7 +214,7 @@ __device__ __forceinline__ int tile_slot_ray(const TraceArgs& a, int t, int slot
   return i * a.nu + j;
 }
 
-template <bool MIXED, int KIND>
+template <bool MIXED, int KIND, int MODE = kModeFlags>
 __global__ __launch_bounds__(256, 2) void k_trace_persistent(TraceArgs a) {
   __shared__ float4 lds_c[4][8][kWaveLanes];
   __shared__ float lds_t[4][8][kWaveLanes];
@@ -273,7 +273,7 @@ __global__ __launch_bounds__(256, 2) void k_trace_persistent(TraceArgs a) {
     if (__ballot(active) == 0ull) break;
     int done = kRunning;
     if (active) {
-      const int code = ray_step<MIXED, KIND>(a, R, C);
+      const int code = ray_step<MIXED, KIND, MODE>(a, R, C);
       if (code != kRunning) {
         finish_ray(a, R);
         active = false;
@@ -344,15 +344,43 @@ hipError_t launch_fill_u32(unsigned* p, unsigned val, long long n, hipStream_t s
   return hipGetLastError();
 }
 
+// The two reduced tracing modes (line of sight; refraction without the tube
+// term) are fixed at compile time for the mixed-precision kernels: without the
+// perturbed retraces the step needs far fewer registers and these kernels run
+// at 3-4 waves per SIMD.  The full method keeps the mode in the call's flags
+// (its compile-time instance spills more and is slower: 993 ms against
+// 979 ms on the structured stack), and so does the all-FP32 variant.
+template <bool MIXED>
+static int launch_mode(uint32_t flags) {
+  if (!MIXED) return kModeFlags;
+  if (!(flags & RT_USE_REFRACTION)) return kModeLos;
+  return (flags & RT_USE_MAGNIFICATION) ? kModeFlags : kModeNoMag;
+}
+
+template <bool MIXED, int KIND, int MODE>
+static hipError_t launch_in_mode(const TraceArgs& a, bool plain, int blocks, hipStream_t s) {
+  if (plain) hipLaunchKernelGGL((k_trace_plain<MIXED, KIND, MODE>), dim3(blocks), dim3(256), 0, s, a);
+  else hipLaunchKernelGGL((k_trace_persistent<MIXED, KIND, MODE>), dim3(blocks), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
 template <bool MIXED, int KIND>
 static hipError_t launch_one(const TraceArgs& a, bool plain, int blocks, hipStream_t s) {
   if (a.flags & RT_CARRIED_TUBE) {
     // carried tubes: mixed precision, one launch per image
     if (!MIXED || !plain) return hipErrorInvalidValue;
     hipLaunchKernelGGL((k_trace_plain<true, KIND, kModeCarried>), dim3(blocks), dim3(256), 0, s, a);
-  } else if (plain) hipLaunchKernelGGL((k_trace_plain<MIXED, KIND>), dim3(blocks), dim3(256), 0, s, a);
-  else hipLaunchKernelGGL((k_trace_persistent<MIXED, KIND>), dim3(blocks), dim3(256), 0, s, a);
-  return hipGetLastError();
+    return hipGetLastError();
+  }
+  if constexpr (!MIXED) {
+    return launch_in_mode<false, KIND, kModeFlags>(a, plain, blocks, s);
+  } else {
+    switch (launch_mode<true>(a.flags)) {
+      case kModeLos: return launch_in_mode<true, KIND, kModeLos>(a, plain, blocks, s);
+      case kModeNoMag: return launch_in_mode<true, KIND, kModeNoMag>(a, plain, blocks, s);
+      default: return launch_in_mode<true, KIND, kModeFlags>(a, plain, blocks, s);
+    }
+  }
 }
 
 hipError_t launch_trace(const TraceArgs& a, bool plain, bool mixed, int blocks, hipStream_t s) {
@@ -363,16 +391,29 @@ hipError_t launch_trace(const TraceArgs& a, bool plain, bool mixed, int blocks, 
              : launch_one<false, RT_GRID_CARTESIAN>(a, plain, blocks, s);
 }
 
-int persistent_blocks_per_cu(bool mixed, int kind) {
+template <bool MIXED, int KIND, int MODE>
+static hipError_t occupancy_of(int* n) {
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, k_trace_persistent<MIXED, KIND, MODE>, 256, 0);
+}
+
+template <int KIND>
+static hipError_t occupancy_mixed(int* n, uint32_t flags) {
+  switch (launch_mode<true>(flags)) {
+    case kModeLos: return occupancy_of<true, KIND, kModeLos>(n);
+    case kModeNoMag: return occupancy_of<true, KIND, kModeNoMag>(n);
+    default: return occupancy_of<true, KIND, kModeFlags>(n);
+  }
+}
+
+int persistent_blocks_per_cu(bool mixed, int kind, uint32_t flags) {
   int n = 0;
   hipError_t e;
   const bool sph = kind == RT_GRID_SPHERICAL_LOGR;
   if (mixed) {
-    e = sph ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_trace_persistent<true, RT_GRID_SPHERICAL_LOGR>, 256, 0)
-            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_trace_persistent<true, RT_GRID_CARTESIAN>, 256, 0);
+    e = sph ? occupancy_mixed<RT_GRID_SPHERICAL_LOGR>(&n, flags) : occupancy_mixed<RT_GRID_CARTESIAN>(&n, flags);
   } else {
-    e = sph ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_trace_persistent<false, RT_GRID_SPHERICAL_LOGR>, 256, 0)
-            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_trace_persistent<false, RT_GRID_CARTESIAN>, 256, 0);
+    e = sph ? occupancy_of<false, RT_GRID_SPHERICAL_LOGR, kModeFlags>(&n)
+            : occupancy_of<false, RT_GRID_CARTESIAN, kModeFlags>(&n);
   }
   if (e != hipSuccess || n < 1) n = 1;
   return n;
