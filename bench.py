@@ -42,8 +42,8 @@ VALU_PEAK_TFLOPS = 78.6
 # valid only for the kernel sources they were taken on (hash below); reported as
 # null as soon as those sources change.
 KERNEL_SOURCES = ("rt_trace.hpp", "rt_kernels.hip", "rt_internal.hpp")
-TRAFFIC = {"sources_sha256_16": "251b99832a2dbd14", "read_bytes": 2787903 * 1024 * 2.000,
-           "write_bytes": 18039 * 1024 * 1.000,
+TRAFFIC = {"sources_sha256_16": "b6b95d5315588b48", "read_bytes": 2765189 * 1024 * 2.000,
+           "write_bytes": 18036 * 1024 * 1.000,
            # SQ_INSTS_VALU + 3 x SQ_INSTS_VALU_TRANS_F32 per ray-step (per lane) of
            # the same profile: the VALU issue slots of the compiled step
            "valu_slots_per_ray_step": 2708}
