@@ -37,10 +37,6 @@ hipError_t launch_stream_read(const float4* buf, long long n4, long long span4, 
   return hipGetLastError();
 }
 
-}  // namespace rt
-
-namespace rt {
-
 // Cell keys of recorded path points: for record s of walk w (the point after
 // step s), the tracer's key (a n1 + b) n2p + c of the cell that holds it, with
 // the tracer's clamping of the r/theta (and Cartesian) cells and the periodic
