@@ -102,6 +102,26 @@ def test_gradient_matches_oracle_small(R, orc, small, mode):
     _compare_grad(f"{mode} ln_te", gte, gte_o)
 
 
+def test_gradient_matches_oracle_polar_observer(R, orc, small):
+    """Observer 20 degrees from the polar axis: the chords have |t_z| > 0.9 and
+    take the y reference axis of Eq. 6, whose adjoint the default view never uses."""
+    cor, m = small
+    freqs = np.array([80e6, 300e6])
+    o, up = (0.3420201433, 0.0, 0.9396926208), (0.0, 1.0, 0.0)
+    n, half = 16, 2.0
+    print("case adjoint polar observer", flush=True)
+    med = orc.OracleMedium.from_corona(cor)
+    kw = dict(ds_max=0.01, n_floor=0.1, max_steps=200000)
+    im_o = orc.make_image(n, half, obs_dir=o, up=up)
+    flags = _oracle_flags(orc, med, orc.make_params(twin_check=True, **kw), im_o, freqs, n * n)
+    w = _weights((2, n, n), 1001, flags)
+    lo, gne_o, gte_o = orc.grad_loss(med, orc.make_params(**kw), im_o, freqs, w)
+    loss, gne, gte, tb = _run(R, m, freqs, R.image_desc(n, half, obs_dir=o, up=up), R.params(**kw), w)
+    assert loss == pytest.approx(lo, rel=1e-5)
+    _compare_grad("polar ln_ne", gne, gne_o)
+    _compare_grad("polar ln_te", gte, gte_o)
+
+
 def _maps_agree(tb_adj, tb_fwd, label):
     """The adjoint traces with its own compiled copy of the step (tracing mode
     fixed at compile time), so its maps equal the forward maps up to rounding."""

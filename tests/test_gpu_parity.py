@@ -130,6 +130,25 @@ def test_structured_ragged_image(R, orc, structured_small, adaptive):
         PU.compare(g["tb"][0, k].reshape(-1), g["info"][0, k].reshape(-1), o, label=f"ragged-{f/1e6:.0f}")
 
 
+@pytest.mark.parametrize("obs_dir,up", [((0.3, -0.8, 0.52), (0.0, 0.0, 1.0)),
+                                         ((0.3420201433, 0.0, 0.9396926208), (0.0, 1.0, 0.0))])
+def test_observer_directions(R, orc, structured_small, obs_dir, up):
+    """An oblique observer, and one 20 degrees from the polar axis, whose chords
+    have |t_z| > 0.9 and so take the y reference axis of Eq. 6."""
+    cor, m = structured_small
+    o = tuple(float(x) for x in np.asarray(obs_dir) / np.linalg.norm(obs_dir))
+    kw = PU.step_kwargs(0.01, 0.1)
+    n, half, freqs = 24, 2.0, [80e6, 300e6]
+    print(f"case observer {o}", flush=True)
+    g = PU.gpu_trace([m], freqs, n, half, kw, image=R.image_desc(n, half, obs_dir=o, up=up))
+    im_o = orc.make_image(n, half, obs_dir=o, up=up)
+    pix = np.arange(n * n, dtype=np.int32)
+    for k, f in enumerate(freqs):
+        res = PU.oracle_trace(orc, cor, f, n, half, pix, kw, image=im_o)
+        s = PU.compare(g["tb"][0, k].reshape(-1), g["info"][0, k].reshape(-1), res, label=f"observer-{f/1e6:.0f}")
+        assert s["flagged"] < 0.25 * s["n"]
+
+
 def test_los_and_no_magnification_modes(R, orc, structured_small):
     cor, m = structured_small
     pix = np.arange(0, 32 * 32, 2, dtype=np.int32)
