@@ -51,7 +51,7 @@ class Params(C.Structure):
                 ("max_steps", C.c_int32), ("twin_check", C.c_int32), ("eta", C.c_double),
                 ("tb_inner", C.c_double), ("tb_sky", C.c_double),
                 ("dp_rtol", C.c_double), ("dp_atol", C.c_double), ("carried_tube", C.c_int32),
-                ("_pad", C.c_int32)]
+                ("_pad", C.c_int32), ("twin_exit_tol", C.c_double)]
 
 
 class Image(C.Structure):
@@ -140,7 +140,7 @@ class OracleMedium:
 
 def make_params(*, stepper=0, refraction=True, magnification=True, no_absorption=False, ds_max=0.005,
                 n_floor=1.0, max_steps=200000, twin_check=False, eta=1e-2, tb_inner=1.0e4, tb_sky=0.0,
-                rtol=1e-12, atol=1e-12, carried_tube=False):
+                rtol=1e-12, atol=1e-12, carried_tube=False, twin_exit_tol=1e-4):
     p = Params()
     p.stepper = stepper
     p.use_refraction = int(refraction)
@@ -151,6 +151,7 @@ def make_params(*, stepper=0, refraction=True, magnification=True, no_absorption
     p.eta, p.tb_inner, p.tb_sky = eta, tb_inner, tb_sky
     p.dp_rtol, p.dp_atol = rtol, atol
     p.carried_tube = int(carried_tube)
+    p.twin_exit_tol = float(twin_exit_tol)
     return p
 
 

@@ -204,6 +204,7 @@ struct Params {
   double dp_rtol, dp_atol;
   int32_t carried_tube;        // 1: tube area from two neighbour rays carried along the whole ray
   int32_t _pad;
+  double twin_exit_tol;        // twin check: exit movement [R_sun] that marks a ray ill-conditioned
 };
 
 struct Image {
@@ -906,7 +907,7 @@ static int grazing_flags(const Medium& m, const Params& P, const Image& im, doub
     Launch T = pixel_launch(im, m.r_max, ju, iv, 1e-6);
     RayOut<double> tw = trace_any(m, P, f, T.r0, T.dir, nullptr, 0, nullptr);
     double dx = tw.exit_pos.x - ro.exit_pos.x, dy = tw.exit_pos.y - ro.exit_pos.y, dz = tw.exit_pos.z - ro.exit_pos.z;
-    if (tw.code != ro.code || std::sqrt(dx * dx + dy * dy + dz * dz) > 1e-4) fl |= GRAZING;
+    if (tw.code != ro.code || std::sqrt(dx * dx + dy * dy + dz * dz) > P.twin_exit_tol) fl |= GRAZING;
   }
   return fl;
 }

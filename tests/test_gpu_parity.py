@@ -69,6 +69,32 @@ def test_persistent_equals_plain_bitwise(R, structured_small):
     assert a["stats"]["ray_steps"] == b["stats"]["ray_steps"]
 
 
+def test_two_different_models_in_one_call(R, orc, structured_small):
+    """Two models with different random fields and active regions in one
+    persistent launch: each image matches the oracle on its own model.  The
+    second model has a ray whose exit moves 97x its launch offset (just under
+    the twin check's 100x), which the FP32 evaluation moves by 1.8e-5 R_sun;
+    this test is about which model each image is traced through, so its oracle
+    flags rays above 50x (twin_exit_tol 5e-5) and keeps the common bars."""
+    cor_a, m_a = structured_small
+    cor_b = corona.structured(nr=64, nt=32, nph=64, r_in=1.0, r_max=30.0, seed=12, n_ar=4, n_feat=256)
+    m_b = R.Model.from_corona(cor_b)
+    kw = PU.step_kwargs(0.01, 0.1)
+    freqs = [60e6, 240e6]
+    n, half = 24, 2.0
+    print("case two models", flush=True)
+    g = PU.gpu_trace([m_a, m_b], freqs, n, half, kw)
+    pix = np.arange(n * n, dtype=np.int32)
+    for mi, cor in enumerate((cor_a, cor_b)):
+        med = orc.OracleMedium.from_corona(cor)
+        P = orc.make_params(twin_check=True, twin_exit_tol=5e-5, **kw)
+        for k, f in enumerate(freqs):
+            res = orc.trace_pixels(med, P, orc.make_image(n, half), f, pix)
+            PU.compare(g["tb"][mi, k].reshape(-1), g["info"][mi, k].reshape(-1), res, label=f"model{mi}-{f/1e6:.0f}")
+    assert not np.array_equal(g["tb"][0], g["tb"][1])
+    m_b.close()
+
+
 def test_every_launch_tuning_gives_the_same_maps(R, structured_small):
     """Every tuning the autotuner may choose (refill threshold, blocks per CU,
     die bands) traces the same bits as the plain per-image launch."""
