@@ -96,15 +96,19 @@ __device__ __forceinline__ float fast_log1pf(float z) {
   return __builtin_amdgcn_logf(1.0f + z) * 0.69314718056f;
 }
 
-// log1p for the small radius increments of the evaluation points: the series
-// to w^5 for |z| <= 1/20 (|w| <= 0.026, relative truncation below 1e-11),
-// fast_log1pf otherwise.
+// log1p for the small radius increments of the evaluation points: the Taylor
+// series to z^7 in Horner form for |z| <= 1/20 (relative truncation below
+// 5e-12; no reciprocal), fast_log1pf otherwise.
 __device__ __forceinline__ float log1p_inc(float z) {
   if (fabsf(z) <= 0.05f) {
-    const float w = z * rcpf(2.0f + z);
-    const float w2 = w * w;
-    const float s = fmaf(fmaf(w2, 1.0f / 5.0f, 1.0f / 3.0f), w2, 1.0f);
-    return 2.0f * w * s;
+    float q = 1.0f / 7.0f;
+    q = fmaf(q, z, -1.0f / 6.0f);
+    q = fmaf(q, z, 1.0f / 5.0f);
+    q = fmaf(q, z, -1.0f / 4.0f);
+    q = fmaf(q, z, 1.0f / 3.0f);
+    q = fmaf(q, z, -1.0f / 2.0f);
+    q = fmaf(q, z, 1.0f);
+    return z * q;
   }
   return fast_log1pf(z);
 }
