@@ -316,9 +316,12 @@ __device__ __forceinline__ void locate(const DevGeom& g, const StepOrigin& O, fl
     const float rhoi = m > 1.0e-24f ? rsqrtf(m) : 0.0f;  // 0 on the polar axis (rho < 1e-12)
     const float rhoq = m * rhoi;
     const float den = rhoq + O.rho;
-    const float drho = den > 0.0f ? e * rcpf(den) : 0.0f;
     const float zq = O.z + dz;
-    x1 = O.f1 + atan2_inc(O.z * drho - O.rho * dz, O.z * zq + O.rho * rhoq) * g.inv_dth;
+    // the angle between (z_i, rho_i) and (z_q, rho_q) from its sine and cosine
+    // parts, both scaled by rho_q + rho_i > 0 (which leaves the angle as it is)
+    // so that rho_q - rho_i = e / (rho_q + rho_i) needs no division; on the
+    // axis both parts vanish
+    x1 = O.f1 + atan2_inc(O.z * e - O.rho * dz * den, den * (O.z * zq + O.rho * rhoq)) * g.inv_dth;
     L.rinv = rsqrtf(O.r2 + c);
     L.rho = rhoq;
     L.axis = rhoq < 1e-12f;
