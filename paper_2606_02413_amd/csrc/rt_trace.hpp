@@ -373,16 +373,20 @@ __device__ __forceinline__ void eval_grad(const DevGeom& g, const float4* nfg, c
   }
   ne = n;
   if constexpr (KIND == RT_GRID_SPHERICAL_LOGR) {
-    // grad = G0/(r dl) r_hat + G1/(r dth) theta_hat + G2/(r sin(theta) dphi) phi_hat
-    const float gt = G1 * g.inv_dth * L.rinv;
-    const float ct = L.z * L.rinv, st = L.rho * L.rinv;
-    const float cph = L.axis ? 1.0f : L.x * L.rhoinv;
-    const float sph = L.axis ? 0.0f : L.y * L.rhoinv;
-    const float gp = L.axis ? 0.0f : G2 * g.inv_dph * L.rhoinv;
-    const float grr = G0 * g.inv_dl * L.rinv * L.rinv;
-    gx = grr * L.x + gt * ct * cph - gp * sph;
-    gy = grr * L.y + gt * ct * sph + gp * cph;
-    gz = grr * L.z - gt * st;
+    // grad = G0/(r dl) r_hat + G1/(r dth) theta_hat + G2/(r sin(theta) dphi) phi_hat,
+    // with r_hat = (x, y, z)/r, theta_hat = (z x/rho, z y/rho, -rho)/r and
+    // phi_hat = (-y, x, 0)/rho collected over the Cartesian components:
+    // g = x c - B y, y c + B x, grr z - A rho with A = G1/(r^2 dth),
+    // B = G2/(rho^2 dphi), c = grr + A z/rho.  On the axis (1/rho taken as 0)
+    // theta_hat is (cos theta, 0, -sin theta) and phi_hat drops out.
+    const float r2i = L.rinv * L.rinv;
+    const float grr = G0 * (g.inv_dl * r2i);
+    const float A = G1 * (g.inv_dth * r2i);
+    const float B = G2 * (g.inv_dph * (L.rhoinv * L.rhoinv));
+    const float c = fmaf(A * L.z, L.rhoinv, grr);
+    gx = fmaf(L.x, c, -B * L.y) + (L.axis ? A * L.z : 0.0f);
+    gy = fmaf(L.y, c, B * L.x);
+    gz = fmaf(grr, L.z, -A * L.rho);
   } else {
     gx = G0 * g.inv_sp[0];
     gy = G1 * g.inv_sp[1];
