@@ -71,6 +71,8 @@ def parse():
     ap.add_argument("--no-plain", action="store_true", help="skip the plain per-frequency timing")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint / forward timing")
+    ap.add_argument("--no-batching", action="store_true",
+                    help="skip the batched-vs-plain record on the 4-model workload (frequency subset)")
     ap.add_argument("--no-probe", action="store_true",
                     help="skip the read-bandwidth probe and the gather replay (for profiling the tracer alone)")
     ap.add_argument("--autotune-freqs", type=int, default=4,
@@ -91,6 +93,15 @@ def parse():
                     help="only run the batching study (batched vs plain on the 4-model 64-frequency workload)")
     ap.add_argument("--precision", action="store_true",
                     help="only run the precision study (mixed vs all-FP32 vs oracle on the 512x256x512 workload)")
+    ap.add_argument("--grad64-oracle", metavar="PATH", default=None,
+                    help="study (CPU only): the oracle's gradient on the 64x32x64 model, 64^2 x 8 image, to PATH")
+    ap.add_argument("--grad64", metavar="PATH", default=None,
+                    help="study: the adjoint on the same configuration vs the oracle gradient stored at PATH")
+    ap.add_argument("--threads", type=int, default=None, help="oracle threads of the CPU-only studies")
+    ap.add_argument("--fit-params", type=int, default=0, metavar="ITERS",
+                    help="study: recover a corona's density scale, T_bg and active-region factors from its maps")
+    ap.add_argument("--gradcheck", action="store_true",
+                    help="study: adjoint vs oracle tape gradient and central differences on the adjoint workload")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (reference for HBM byte counters)")
@@ -112,31 +123,64 @@ def calibrate_copy():
     print(json.dumps({"copy_bytes_per_launch": src.numel() * 4, "launches": 4}), flush=True)
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(cor, wl, seconds):
-    """The FP64 oracle, as it stands, on a bounded seeded pixel sample."""
+    """The FP64 oracle, as it stands, built for this host (g++ -O3 -march=native)
+    and timed on a bounded seeded pixel sample of the workload: on all host
+    threads the process may use (at most 16, the host share of one GPU), then on
+    one thread.  Each leg runs about `seconds` of CPU work."""
     from oracle import oracle as O
     from paper_2606_02413_amd import corona
+    t_build = time.perf_counter()
+    O.build(native=True)
+    O.use_library(O.NATIVE_LIB_PATH)
+    t_build = time.perf_counter() - t_build
     med = O.OracleMedium.from_corona(cor)
     P = O.make_params(ds_max=wl.ds_max, n_floor=wl.n_floor, max_steps=wl.max_steps)
     im = O.make_image(wl.n_pix, wl.half_width)
-    threads = O.default_threads()
     order = corona.seeded_pixels(wl.n_pix, 4096, 3000)
-    steps = 0
-    rays = 0
-    t0 = time.perf_counter()
-    k = 0
-    chunk = 32
-    while time.perf_counter() - t0 < seconds and k < len(order):
-        pix = order[k:k + chunk]
-        for f in wl.freqs:
-            r = O.trace_pixels(med, P, im, f, pix, n_threads=threads)
-            steps += int(r["n_steps"].sum())
-            rays += len(pix)
-        k += chunk
-    dt = time.perf_counter() - t0
-    return {"value": steps / dt, "unit": "ray-steps/s", "cores": threads, "kind": "oracle",
-            "sample": f"{rays} rays ({rays // len(wl.freqs)} seeded pixels x {len(wl.freqs)} freq) of the "
-                      f"structured workload, {steps} ray-steps in {dt:.1f} s"}
+
+    def leg(threads, budget, start, chunk):
+        steps = rays = 0
+        t0 = time.perf_counter()
+        k = start
+        while time.perf_counter() - t0 < budget and k < len(order):
+            pix = order[k:k + chunk]
+            for f in wl.freqs:
+                r = O.trace_pixels(med, P, im, f, pix, n_threads=threads)
+                steps += int(r["n_steps"].sum())
+                rays += len(pix)
+            k += chunk
+        dt = time.perf_counter() - t0
+        return {"ray_steps_per_s": steps / dt, "threads": threads, "rays": rays, "ray_steps": steps,
+                "seconds": round(dt, 2), "pixels": (k - start)}
+
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        affinity = os.cpu_count() or 1
+    threads = max(1, min(affinity, 16))
+    allc = leg(threads, seconds, 0, 4 * threads)
+    one = leg(1, 0.6 * seconds, 2048, 2)
+    return {"value": allc["ray_steps_per_s"], "unit": "ray-steps/s", "cores": threads, "kind": "oracle",
+            "sample": f"{allc['rays']} rays ({allc['pixels']} seeded pixels x {len(wl.freqs)} freq) of the "
+                      f"structured workload, {allc['ray_steps']} ray-steps in {allc['seconds']} s on {threads} threads",
+            "one_core": {"value": one["ray_steps_per_s"], "unit": "ray-steps/s",
+                         "sample": f"{one['rays']} rays ({one['pixels']} other seeded pixels x {len(wl.freqs)} "
+                                   f"freq), {one['ray_steps']} ray-steps in {one['seconds']} s on 1 thread"},
+            "parallel_speedup": allc["ray_steps_per_s"] / one["ray_steps_per_s"],
+            "nproc": os.cpu_count(), "affinity_cpus": affinity, "cpu_model": cpu_model(),
+            "build": O.build_flags(native=True), "build_s": round(t_build, 1)}
 
 
 def adjoint_ratio(R, torch, model, stream, reps=2):
@@ -173,13 +217,18 @@ def adjoint_ratio(R, torch, model, stream, reps=2):
             "loss": float(adj["loss"].cpu()[0])}
 
 
-def precision_study(n_pixels=4096, seconds_note=True):
-    """Mixed precision vs all-FP32 vs the FP64 oracle on the precision workload:
+PRECISION_VARIANTS = (("default", dict()), ("fp32_step", dict(fp32_step=True)), ("all_fp32", dict(all_fp32=True)))
+
+
+def precision_study(n_pixels=4096):
+    """The three precision variants vs the FP64 oracle on the precision workload:
     512x256x512 model (r 1-30, 32 active regions, seed 4), 2048^2 image over
     +/-3 R_sun, 16 frequencies 40-800 MHz; the oracle traces 4096 pixels drawn
-    with seed 3000 at every frequency (rays it flags as grazing, marginal or
-    polar are counted and left out of the error statistics).  Prints one JSON
-    line with the per-map max / median relative error of both variants."""
+    with seed 3000 at every frequency.  Variants: default (FP64 state, area and
+    transfer), fp32_step (FP32 state, increments and grid index; FP64 area and
+    transfer), all_fp32.  Per map: max / median relative T_b error over the rays
+    that end with the oracle's termination code, also over unflagged rays only,
+    and the oracle's flag counts per category.  Prints one JSON line."""
     import torch
     from oracle import oracle as O
     from paper_2606_02413_amd import corona, rtsun as R
@@ -193,21 +242,23 @@ def precision_study(n_pixels=4096, seconds_note=True):
     pix = corona.seeded_pixels(wl.n_pix, n_pixels, 3000)
     pix_t = torch.from_numpy(pix.astype(np.int64)).cuda()
     res = {}
-    for name, fp32 in (("mixed", False), ("all_fp32", True)):
-        prm = R.params(ds_max=wl.ds_max, n_floor=wl.n_floor, max_steps=wl.max_steps, all_fp32=fp32)
-        out = R.trace_maps([model], wl.freqs, im, prm, info=False, stats=True)
+    for name, flags in PRECISION_VARIANTS:
+        prm = R.params(ds_max=wl.ds_max, n_floor=wl.n_floor, max_steps=wl.max_steps, **flags)
+        out = R.trace_maps([model], wl.freqs, im, prm, info=True, stats=True)
         torch.cuda.synchronize()
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record()
-        R.trace_maps([model], wl.freqs, im, prm, info=False, stats=True, out=out)
+        R.trace_maps([model], wl.freqs, im, prm, info=True, stats=True, out=out)
         e1.record()
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1)
         progress(f"precision {name}: {ms:.0f} ms")
         steps = int(R.decode_stats(out["stats"])["ray_steps"])
         tb = out["tb"][0].reshape(len(wl.freqs), -1)[:, pix_t].double().cpu().numpy()
-        res[name] = {"tb": tb, "ms": ms, "ray_steps": steps}
+        info = out["info"][0].reshape(len(wl.freqs), -1, 32)[:, pix_t]
+        code = R.decode_info(info)["code"].astype(np.int32).reshape(len(wl.freqs), -1)
+        res[name] = {"tb": tb, "code": code, "ms": ms, "ray_steps": steps}
         del out
         torch.cuda.empty_cache()
     med = O.OracleMedium.from_corona(cor)
@@ -219,24 +270,31 @@ def precision_study(n_pixels=4096, seconds_note=True):
         o = O.trace_pixels(med, P, imo, f, pix.astype(np.int32))
         progress(f"precision oracle {f / 1e6:.1f} MHz done")
         ok = o["flags"] == 0
-        row = {"freq_MHz": round(f / 1e6, 3), "flagged": int((~ok).sum())}
-        for name in ("mixed", "all_fp32"):
+        row = {"freq_MHz": round(f / 1e6, 3), "flagged": int((~ok).sum()),
+               "grazing": int(((o["flags"] & O.GRAZING) != 0).sum()),
+               "marginal": int(((o["flags"] & O.MARGINAL) != 0).sum()),
+               "polar": int(((o["flags"] & O.POLAR) != 0).sum()), "polar_only": int((o["flags"] == O.POLAR).sum())}
+        for name, _ in PRECISION_VARIANTS:
+            same = res[name]["code"][k] == o["code"]
             rel = np.abs(res[name]["tb"][k] - o["tb"]) / np.maximum(np.abs(o["tb"]), 1.0)
-            row[name + "_max_rel"] = float(rel[ok].max())
-            row[name + "_median_rel"] = float(np.median(rel[ok]))
-            row[name + "_max_rel_all_rays"] = float(rel.max())
-            row[name + "_over_1e-3_all_rays"] = int((rel > 1e-3).sum())
+            row[name + "_max_rel"] = float(rel[same].max())
+            row[name + "_median_rel"] = float(np.median(rel[same]))
+            row[name + "_max_rel_unflagged"] = float(rel[ok & same].max())
+            row[name + "_median_rel_unflagged"] = float(np.median(rel[ok & same]))
+            row[name + "_code_changes"] = int((~same).sum())
+            row[name + "_over_1e-3"] = int((same & (rel > 1e-3)).sum())
         maps.append(row)
     t_orc = time.perf_counter() - t1
     line = {"study": "precision", "workload": "512x256x512 model (r 1-30 R_sun, 32 active regions, seed 4), "
             "2048^2 image +/-3 R_sun, 16 freq 40-800 MHz, ds_max 0.01, n_floor 0.1",
             "oracle_pixels": f"{n_pixels} seeded (seed 3000) x 16 freq", "maps": maps,
-            "worst_mixed_max_rel": max(m["mixed_max_rel"] for m in maps),
-            "worst_all_fp32_max_rel": max(m["all_fp32_max_rel"] for m in maps),
-            "mixed": {"ms": res["mixed"]["ms"], "ray_steps_per_s": res["mixed"]["ray_steps"] / res["mixed"]["ms"] * 1e3},
-            "all_fp32": {"ms": res["all_fp32"]["ms"],
-                         "ray_steps_per_s": res["all_fp32"]["ray_steps"] / res["all_fp32"]["ms"] * 1e3},
-            "model_generation_s": t_model, "oracle_s": t_orc, "oracle_threads": O.default_threads()}
+            "oracle_s": round(t_orc, 1), "oracle_threads": O.default_threads(), "model_s": round(t_model, 1)}
+    for name, _ in PRECISION_VARIANTS:
+        line[name] = {"ms": res[name]["ms"], "ray_steps": res[name]["ray_steps"],
+                      "ray_steps_per_s": res[name]["ray_steps"] / res[name]["ms"] * 1e3,
+                      "worst_max_rel": max(m[name + "_max_rel"] for m in maps),
+                      "worst_median_rel": max(m[name + "_median_rel"] for m in maps),
+                      "code_changes": sum(m[name + "_code_changes"] for m in maps)}
     print(json.dumps(line), flush=True)
     model.close()
 
@@ -457,15 +515,225 @@ def fit_study(iters):
     model.close()
 
 
-def batching_study():
+GRAD64_FIELDS = ("flags", "weights", "grad_ln_ne", "grad_ln_te")
+
+
+def grad64_config():
+    """The oracle-gradient check of the adjoint at its configured size: the
+    adjoint workload's generator (random field and 8 active regions, seed 0,
+    r 1-30 R_sun) on a 64x32x64 grid, its 64^2 image over +/-3 R_sun at the 8
+    frequencies 40-800 MHz, ds_max 0.01, n_floor 0.1, weights w ~ U[0, 1)
+    (seed 1000) on every ray."""
+    from paper_2606_02413_amd import corona
+    cor = corona.structured(nr=64, nt=32, nph=64, r_in=1.0, r_max=30.0, seed=0, n_feat=512)
+    freqs = corona.log_freqs(8)
+    w = corona.seeded_weights((8, 64, 64), 1000)
+    return cor, freqs, 64, 3.0, w
+
+
+def grad64_oracle(path, threads=None):
+    """Oracle side (CPU only): every ray's flags (twin check), weights zeroed on
+    flagged rays (their discrete path may differ between FP32 and FP64
+    evaluation), then the loss and its gradient by per-ray tapes.  Writes the
+    flags, weights and gradients to `path` (numpy archive)."""
+    from oracle import oracle as O
+    cor, freqs, n, half, w = grad64_config()
+    med = O.OracleMedium.from_corona(cor)
+    kw = dict(ds_max=0.01, n_floor=0.1, max_steps=200000)
+    im = O.make_image(n, half)
+    pix = np.arange(n * n, dtype=np.int32)
+    t0 = time.perf_counter()
+    flags = np.stack([O.trace_pixels(med, O.make_params(twin_check=True, **kw), im, f, pix, n_threads=threads)["flags"]
+                      for f in freqs]).reshape(w.shape)
+    w = np.where(flags != 0, np.float32(0.0), w).astype(np.float32)
+    progress(f"grad64 oracle: flags in {time.perf_counter() - t0:.0f} s, {int((flags != 0).sum())} flagged rays")
+    t1 = time.perf_counter()
+    loss, gne, gte = O.grad_loss(med, O.make_params(**kw), im, freqs, w, n_threads=threads)
+    progress(f"grad64 oracle: gradient in {time.perf_counter() - t1:.0f} s")
+    with open(path, "wb") as fh:
+        np.savez_compressed(fh, flags=flags, weights=w, grad_ln_ne=gne, grad_ln_te=gte, loss=np.array([loss]),
+                            seconds=np.array([time.perf_counter() - t0]), threads=np.array([threads or 0]))
+    print(json.dumps({"study": "grad64-oracle", "loss": loss, "flagged": int((flags != 0).sum()),
+                      "seconds": time.perf_counter() - t0}), flush=True)
+
+
+def grad_compare(label, g_gpu, g_orc):
+    g = g_gpu.astype(np.float64)
+    scale = float(np.abs(g_orc).max())
+    d = np.abs(g - g_orc)
+    nz = g_orc != 0
+    return {"field": label, "max_abs_diff_over_max": float(d.max() / scale),
+            "rel_l2": float(np.linalg.norm(g - g_orc) / np.linalg.norm(g_orc)),
+            "frac_within_1e-4_of_max": float(np.mean(d[nz] <= 1e-4 * scale)),
+            "nonzero": int(nz.sum()), "same_support": bool(np.array_equal(g_orc == 0, g == 0))}
+
+
+def grad64_compare(path):
+    """GPU side: rt_trace_adjoint on the configuration of grad64_config with the
+    weights the oracle used (read from `path`), compared vertex by vertex with
+    the oracle's gradient."""
+    import torch
+    from paper_2606_02413_amd import rtsun as R
+    with open(path, "rb") as fh:
+        z = np.load(fh)
+        ref = {k: z[k] for k in z.files}
+    cor, freqs, n, half, _ = grad64_config()
+    m = R.Model.from_corona(cor)
+    prm = R.params(ds_max=0.01, n_floor=0.1, max_steps=200000)
+    w = torch.from_numpy(ref["weights"].astype(np.float32)).cuda()
+    res = R.trace_adjoint(m, freqs, R.image_desc(n, half), prm, w)
+    torch.cuda.synchronize()
+    loss = float(res["loss"].cpu()[0])
+    out = {"study": "grad64", "config": "64x32x64 structured (seed 0, r 1-30), 64^2 x 8 freq, w ~ U[0,1) seed 1000, "
+                                       "flagged rays weight 0",
+           "flagged_rays": int((ref["flags"] != 0).sum()), "rays": int(ref["flags"].size),
+           "loss_gpu": loss, "loss_oracle": float(ref["loss"][0]),
+           "loss_rel_diff": abs(loss / float(ref["loss"][0]) - 1),
+           "ln_ne": grad_compare("ln_ne", res["grad_ln_ne"].cpu().numpy(), ref["grad_ln_ne"]),
+           "ln_te": grad_compare("ln_te", res["grad_ln_te"].cpu().numpy(), ref["grad_ln_te"]),
+           "oracle_seconds": float(ref["seconds"][0]), "oracle_threads": int(ref["threads"][0])}
+    print(json.dumps(out), flush=True)
+    m.close()
+
+
+def gradcheck_study(n_pixels=64, n_cells=200, h=1e-3):
+    """Central differences of the loss at its configured size: the adjoint
+    workload (256x128x256 structured model, seed 0; 256^2 image over +/-3 R_sun;
+    the 8 frequencies), loss = sum w T_b with w ~ U[0, 1) (seed 1000) on the rays
+    of `n_pixels` seeded pixels (seed 2001) at every frequency and 0 elsewhere
+    (and 0 on rays the oracle flags).  (1) The GPU adjoint vs the oracle's
+    tape gradient at every vertex.  (2) `n_cells` vertices drawn (seed 2000) from
+    the top decile of |oracle d loss / d ln n_e| and as many of |d loss / d ln T|:
+    the oracle's forward loss at ln value +-h (the FP32 value e^{+-h} x, the
+    difference divided by the realized ln difference), against the adjoint and
+    the tape gradient.  Each FD outlier is checked for a discrete event in the
+    oracle between +h and -h (a changed step count or termination code) and for
+    the FD's own non-smoothness (FD at h/2 against FD at h)."""
+    import torch
+    from oracle import oracle as O
+    from paper_2606_02413_amd import corona, rtsun as R
+    wl = corona.workload("adjoint")
+    cor = wl.models(device="cuda")[0]
+    freqs = wl.freqs
+    n = wl.n_pix
+    kw = dict(ds_max=wl.ds_max, n_floor=wl.n_floor, max_steps=wl.max_steps)
+    pix = corona.seeded_pixels(n, n_pixels, 2001)
+    wfull = corona.seeded_weights((len(freqs), n, n), 1000)
+    med = O.OracleMedium.from_corona(cor)
+    imo = O.make_image(n, wl.half_width)
+    t0 = time.perf_counter()
+    flags = np.stack([O.trace_pixels(med, O.make_params(twin_check=True, **kw), imo, f, pix)["flags"] for f in freqs])
+    w = np.zeros_like(wfull)
+    for k in range(len(freqs)):
+        w[k].flat[pix] = np.where(flags[k] != 0, np.float32(0.0), wfull[k].flat[pix])
+    progress(f"gradcheck: {int((flags != 0).sum())} of {flags.size} sampled rays flagged ({time.perf_counter() - t0:.0f} s)")
+    t1 = time.perf_counter()
+    loss_o, gne_o, gte_o = O.grad_loss(med, O.make_params(**kw), imo, freqs, w)
+    t_tape = time.perf_counter() - t1
+    progress(f"gradcheck: oracle tape gradient in {t_tape:.0f} s")
+    m = R.Model.from_corona(cor)
+    res = R.trace_adjoint(m, freqs, R.image_desc(n, wl.half_width), R.params(**kw), torch.from_numpy(w).cuda())
+    torch.cuda.synchronize()
+    gne = res["grad_ln_ne"].cpu().numpy().astype(np.float64)
+    gte = res["grad_ln_te"].cpu().numpy().astype(np.float64)
+    loss_g = float(res["loss"].cpu()[0])
+    m.close()
+    out = {"study": "gradcheck", "workload": "adjoint workload (256x128x256, 256^2 x 8 freq), sparse weights on "
+           f"{n_pixels} seeded pixels x {len(freqs)} freq", "h": h, "loss_oracle": loss_o, "loss_gpu": loss_g,
+           "loss_rel_diff": abs(loss_g / loss_o - 1), "flagged_rays": int((flags != 0).sum()),
+           "oracle_tape_s": round(t_tape, 1),
+           "adjoint_vs_tape": [grad_compare("ln_ne", gne, gne_o), grad_compare("ln_te", gte, gte_o)]}
+    rng = np.random.Generator(np.random.PCG64(2000))
+    sel_pix = np.asarray(pix, dtype=np.int32)
+
+    def loss_of(med_x):
+        tot = 0.0
+        info = []
+        for k, f in enumerate(freqs):
+            r = O.trace_pixels(med_x, O.make_params(**kw), imo, f, sel_pix)
+            tot += float((w[k].flat[sel_pix].astype(np.float64) * r["tb"]).sum())
+            info.append(np.stack([r["n_steps"], r["code"]]))
+        return tot, np.stack(info)
+
+    fields = []
+    for name, g_orc, g_gpu, arr in (("ln_ne", gne_o, gne, cor.ne), ("ln_te", gte_o, gte, cor.te)):
+        mag = np.abs(g_orc).reshape(-1)
+        nz = np.flatnonzero(mag > 0)
+        top = nz[mag[nz] >= np.quantile(mag[nz], 0.9)]
+        cells = np.sort(rng.choice(top, size=min(n_cells, top.size), replace=False))
+        flat = arr.reshape(-1)
+        rows = []
+        t2 = time.perf_counter()
+        for v in cells:
+            x0 = flat[v]
+
+            def fd(hh):
+                xp, xm = np.float32(x0 * np.exp(hh)), np.float32(x0 * np.exp(-hh))
+                flat[v] = xp
+                lp, ip = loss_of(O.OracleMedium.from_corona(cor))
+                flat[v] = xm
+                lm, im_ = loss_of(O.OracleMedium.from_corona(cor))
+                flat[v] = x0
+                return (lp - lm) / (np.log(np.float64(xp)) - np.log(np.float64(xm))), bool(np.array_equal(ip, im_))
+
+            d1, same1 = fd(h)
+            go, gg = float(g_orc.reshape(-1)[v]), float(g_gpu.reshape(-1)[v])
+            row = {"vertex": int(v), "fd": d1, "tape": go, "adjoint": gg,
+                   "adjoint_vs_fd": abs(gg - d1) / abs(d1) if d1 != 0 else float("inf"),
+                   "tape_vs_fd": abs(go - d1) / abs(d1) if d1 != 0 else float("inf"),
+                   "steps_and_codes_unchanged": same1}
+            if row["adjoint_vs_fd"] > 1e-4:
+                d2, same2 = fd(0.5 * h)
+                row["fd_half_h"] = d2
+                row["fd_h_vs_half_h"] = abs(d1 - d2) / abs(d2) if d2 != 0 else float("inf")
+                row["adjoint_vs_fd_half_h"] = abs(gg - d2) / abs(d2) if d2 != 0 else float("inf")
+            rows.append(row)
+        t_fd = time.perf_counter() - t2
+        within = [r["adjoint_vs_fd"] <= 1e-4 for r in rows]
+        outl = [r for r in rows if r["adjoint_vs_fd"] > 1e-4]
+        fields.append({"field": name, "cells": len(rows), "fraction_within_1e-4": float(np.mean(within)),
+                       "tape_fraction_within_1e-4": float(np.mean([r["tape_vs_fd"] <= 1e-4 for r in rows])),
+                       "median_adjoint_vs_fd": float(np.median([r["adjoint_vs_fd"] for r in rows])),
+                       "outliers": outl, "fd_seconds": round(t_fd, 1)})
+        progress(f"gradcheck {name}: {fields[-1]['fraction_within_1e-4']:.3f} within 1e-4, "
+                 f"{len(outl)} outliers, {t_fd:.0f} s")
+    out["fd"] = fields
+    print(json.dumps(out), flush=True)
+
+
+def fit_params_study(iters):
+    """Recover a known synthetic corona's density scale, background temperature
+    and 8 active-region density factors from its 8-frequency maps: the structured
+    model's generator on a 128x64x128 grid (r 1-30, seed 5), 128^2 image over
+    +/-1.5 R_sun, 8 frequencies 40-800 MHz; the fit starts from s = 0.25,
+    T_bg = 1.6 MK, A_k = 4.5."""
+    from paper_2606_02413_amd import corona
+    from paper_2606_02413_amd.fitting import fit_params
+    kw = dict(nr=128, nt=64, nph=128, r_in=1.0, r_max=30.0, seed=5, n_ar=8, n_feat=512)
+    start = np.concatenate([[0.25, math.log(1.6e6)], np.full(8, math.log(3.5))])
+    t0 = time.perf_counter()
+    truth, hist, th = fit_params(kw, 128, 1.5, corona.log_freqs(8), iters, 0.03, start, log=progress)
+    a_true = 1.0 + np.exp(truth[2:])
+    a_fit = 1.0 + np.exp(th[2:])
+    print(json.dumps({"study": "fit-params", "model": "128x64x128 structured (r 1-30, seed 5, 8 active regions)",
+                      "image": "128^2 over +/-1.5 R_sun x 8 freq", "iters": iters, "seconds": time.perf_counter() - t0,
+                      "truth": {"s": 0.0, "T_bg": 1.2e6, "A": a_true.tolist()},
+                      "fit": {"s": float(th[0]), "T_bg": float(math.exp(th[1])), "A": a_fit.tolist()},
+                      "abs_err_s": abs(float(th[0])), "rel_err_T_bg": abs(math.exp(th[1]) / 1.2e6 - 1),
+                      "rel_err_A": (np.abs(a_fit / a_true - 1)).tolist(),
+                      "history": hist[::5] + [hist[-1]]}), flush=True)
+
+
+def batching_measure(R, torch, freq_stride=1, refills=(64,)):
     """Batched (one persistent launch over every model, frequency and tile) vs
     plain (one launch per image) on (a) the batched workload: the structured
-    model with seeds 0-3, 64 frequencies 40-800 MHz, 1024^2 image over +/-3 R_sun;
-    (b) a long-span variant: the spherically symmetric 64x32x64 model (r 1-3),
-    64 frequencies, 1024^2 image over +/-2.5 R_sun, ds_max 0.005, n_floor 1, whose
-    rays take 63 to ~1,100 steps.  (b) is also run with several refill thresholds."""
-    import torch
-    from paper_2606_02413_amd import corona, rtsun as R
+    model with seeds 0-3, 64 frequencies 40-800 MHz (every `freq_stride`-th of
+    them), 1024^2 image over +/-3 R_sun; (b) a long-span variant: the spherically
+    symmetric 64x32x64 model (r 1-3), 64 frequencies, 1024^2 image over
+    +/-2.5 R_sun, ds_max 0.005, n_floor 1, whose rays take 63 to ~1,100 steps,
+    with the given refill thresholds.  Each path is timed once, after one
+    untimed pass of the same call; the maps are compared bit for bit."""
+    from paper_2606_02413_amd import corona
     stream = torch.cuda.current_stream()
 
     def timed(fn):
@@ -477,34 +745,41 @@ def batching_study():
         torch.cuda.synchronize()
         return e0.elapsed_time(e1)
 
-    out = {"study": "batching"}
+    out = {}
     wl = corona.workload("batched")
-    models = [R.Model.from_corona(c) for c in wl.models(device="cuda")]
-    progress("batched workload models loaded")
+    freqs = wl.freqs[::freq_stride]
+    cors = wl.models(device="cuda")
+    models = [R.Model.from_corona(c) for c in cors]
+    del cors
+    progress(f"batched workload: {len(models)} models, {len(freqs)} of {len(wl.freqs)} frequencies")
     im = R.image_desc(wl.n_pix, wl.half_width)
     kw = dict(ds_max=wl.ds_max, n_floor=wl.n_floor, max_steps=wl.max_steps)
-    # a pass takes minutes, so each path is timed once, without a warm-up pass
-    # (allocation of the library's per-call tables is milliseconds)
-    res = {}
-    b_ms = timed(lambda: R.trace_maps(models, wl.freqs, im, R.params(**kw), info=False, stats=True, out=res))
+    res = R.trace_maps(models, freqs, im, R.params(**kw), info=False, stats=True)
+    torch.cuda.synchronize()
+    b_ms = timed(lambda: R.trace_maps(models, freqs, im, R.params(**kw), info=False, stats=True, out=res))
     steps = int(R.decode_stats(res["stats"])["ray_steps"])
     progress(f"batched {b_ms:.0f} ms")
-    p_ms = 0.0
     tb_b = res["tb"]
+    r1 = R.trace_maps([models[0]], freqs, im, R.params(plain=True, **kw), info=False, stats=False)
+    torch.cuda.synchronize()
+    p_ms = 0.0
     same = True
-    for k, mdl in enumerate(models):  # plain: 64 launches per model, timed per model
-        r1 = {}
-        p_ms += timed(lambda: R.trace_maps([mdl], wl.freqs, im, R.params(plain=True, **kw), info=False,
+    for k, mdl in enumerate(models):  # plain: one launch per (model, frequency) image
+        p_ms += timed(lambda: R.trace_maps([mdl], freqs, im, R.params(plain=True, **kw), info=False,
                                            stats=False, out=r1))
         same = same and bool(torch.equal(r1["tb"][0], tb_b[k]))
         progress(f"plain model {k}: cumulative {p_ms:.0f} ms")
-        del r1
-    out["batched_workload"] = {"rays": int(tb_b.numel()), "ray_steps": steps, "batched_ms": b_ms, "plain_ms": p_ms,
-                               "batched_over_plain": p_ms / b_ms, "ray_steps_per_s_batched": steps / b_ms * 1e3,
-                               "rays_per_s_batched": tb_b.numel() / b_ms * 1e3, "bitwise_equal": same}
+    maps = int(tb_b.shape[0] * tb_b.shape[1])
+    out["batched_workload"] = {
+        "workload": f"{len(models)} structured models (seeds 0-3) x {len(freqs)} freq (every {freq_stride}th of 64, "
+                    f"40-800 MHz) x {wl.n_pix}^2, ds_max {wl.ds_max}, n_floor {wl.n_floor}",
+        "rays": int(tb_b.numel()), "ray_steps": steps, "batched_ms": b_ms, "plain_ms": p_ms,
+        "batched_over_plain": p_ms / b_ms, "ray_steps_per_s_batched": steps / b_ms * 1e3,
+        "maps_1024sq_per_s_batched": maps / b_ms * 1e3, "maps_1024sq_per_s_plain": maps / p_ms * 1e3,
+        "maps_512sq_equiv_per_s_batched": tb_b.numel() / 262144 / b_ms * 1e3, "bitwise_equal": same}
     for m in models:
         m.close()
-    del res, tb_b
+    del res, tb_b, r1
     torch.cuda.empty_cache()
     # (b) long-span variant
     cor = corona.spherically_symmetric()
@@ -515,11 +790,14 @@ def batching_study():
     r1 = R.trace_maps([mdl], freqs, im, R.params(plain=True, **kw), info=False, stats=True)
     torch.cuda.synchronize()
     p_ms = timed(lambda: R.trace_maps([mdl], freqs, im, R.params(plain=True, **kw), info=False, stats=True, out=r1))
-    steps = int(R.decode_stats(r1["stats"])["ray_steps"])
     st = R.decode_stats(r1["stats"])
-    span = {"plain_ms": p_ms, "ray_steps": steps, "max_steps": int(st["max_steps"]),
+    steps = int(st["ray_steps"])
+    span = {"workload": "spherically symmetric 64x32x64 (r 1-3), 64 freq x 1024^2 over +/-2.5 R_sun, "
+                        "ds_max 0.005, n_floor 1",
+            "plain_ms": p_ms, "ray_steps": steps, "max_steps": int(st["max_steps"]),
             "mean_steps_per_traced_ray": steps / max(1, int(r1["tb"].numel()) - int(st["code_count"][3]))}
-    for thr in (64, 32, 8, 1):
+    saved = R.get_tuning(mdl.device)
+    for thr in refills:
         R.set_tuning(R.tuning(refill_min_idle=thr), mdl.device)
         r2 = R.trace_maps([mdl], freqs, im, R.params(**kw), info=False, stats=False)
         torch.cuda.synchronize()
@@ -529,23 +807,36 @@ def batching_study():
         span[f"bitwise_equal_refill{thr}"] = bool(torch.equal(r2["tb"], r1["tb"]))
         progress(f"long-span refill {thr}: {ms:.0f} ms (plain {p_ms:.0f})")
         del r2
-    R.set_tuning(R.tuning(), mdl.device)
+    R.set_tuning(saved, mdl.device)
     out["long_span_variant"] = span
-    print(json.dumps(out), flush=True)
     mdl.close()
+    del r1
+    torch.cuda.empty_cache()
+    return out
 
 
-def l2_gather_roofline(R, torch, model, wl, rate):
+def batching_study():
+    """The full batched workload (all 64 frequencies) and the long-span variant
+    at several refill thresholds."""
+    import torch
+    from paper_2606_02413_amd import rtsun as R
+    out = {"study": "batching"}
+    out.update(batching_measure(R, torch, freq_stride=1, refills=(64, 32, 8, 1)))
+    print(json.dumps(out), flush=True)
+
+
+def l2_gather_roofline(R, torch, model, wl, rate, bw, replay=True):
     """The L2-gather roofline of the tracer: R_L2 from the measured streaming
     read bandwidth of the L2 and the layout's gathered bytes per ray-step, and
     R_gather from the gather-only replay of the model's recorded walks."""
-    bw = R.read_bandwidths(model.device)
     r_l2 = bw["l2_GBps"] * 1e9 / GATHER_BYTES_PER_RAY_STEP
     gathers = {"B_L2_GBps": round(bw["l2_GBps"], 1), "bytes_per_ray_step": GATHER_BYTES_PER_RAY_STEP,
                "R_L2_ray_steps_per_s": r_l2, "frac": round(rate / r_l2, 4),
                "frac_at_448_B_per_ray_step": round(rate / (bw["l2_GBps"] * 1e9 / GATHER_BYTES_PER_RAY_STEP_NE_ONLY), 4),
                "gather_GBps_equivalent": round(rate * GATHER_BYTES_PER_RAY_STEP / 1e9, 1),
                "infinity_cache_GBps": round(bw["infinity_cache_GBps"], 1), "hbm_GBps": round(bw["hbm_GBps"], 1)}
+    if not replay:
+        return gathers
     # gather-only replay of the same model's recorded walks (128^2 pixels x the 8
     # frequencies): the rate the memory system serves this layout's gathers at
     rep = R.gather_replay(model, wl.freqs, R.image_desc(128, wl.half_width),
@@ -575,6 +866,18 @@ def main():
         return
     if args.spectrum:
         spectrum_study()
+        return
+    if args.grad64_oracle:
+        grad64_oracle(args.grad64_oracle, args.threads)
+        return
+    if args.fit_params > 0:
+        fit_params_study(args.fit_params)
+        return
+    if args.gradcheck:
+        gradcheck_study()
+        return
+    if args.grad64:
+        grad64_compare(args.grad64)
         return
     if args.fit > 0:
         fit_study(args.fit)
@@ -671,19 +974,32 @@ def main():
         traffic = {"read_bytes": TRAFFIC["read_bytes"], "write_bytes": TRAFFIC["write_bytes"],
                    "bytes": TRAFFIC["read_bytes"] + TRAFFIC["write_bytes"],
                    "GB/s": round((TRAFFIC["read_bytes"] + TRAFFIC["write_bytes"]) / (ms_per_step * 1e-3) / 1e9, 2)}
-    roofline = {"bound": "alu", "achieved": round(achieved_tflops, 3), "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved_tflops / VALU_PEAK_TFLOPS, 4), "traffic": traffic,
-                "kernel": "k_trace_persistent<mixed, spherical>", "flops_per_ray_step": FLOPS_PER_RAY_STEP,
-                "kernel_ms": round(ms_per_step, 3)}
-    # the other two rooflines of the tracer: VALU issue (from the profile's
-    # counters, for the same kernel sources) and the gathers against the
-    # measured streaming-read bandwidth of the L2 (probe kernel, this run)
+    # Headline: the L2-gather roofline.  Algorithmic bytes per ray-step = 448
+    # (13 evaluations of the model, 12 of them 8 corners x 4 B of n_e and one 8
+    # corners x (n_e, T)); achieved = 448 B x ray-steps per launch / launch time;
+    # peak = the chip's streaming-read bandwidth out of L2, measured in this run
+    # by the library's probe kernel.
+    bw = R.read_bandwidths(model.device)
+    b_l2 = bw["l2_GBps"]
+    achieved_gbps = GATHER_BYTES_PER_RAY_STEP_NE_ONLY * rate / 1e9
+    roofline = {"bound": "l2_gather", "achieved": round(achieved_gbps, 1), "peak": round(b_l2, 1), "unit": "GB/s",
+                "frac": round(achieved_gbps / b_l2, 4), "traffic": traffic,
+                "kernel": "k_trace_persistent<mixed, spherical>",
+                "bytes_per_ray_step": GATHER_BYTES_PER_RAY_STEP_NE_ONLY, "ray_steps_per_launch": steps_per_pass,
+                "kernel_ms": round(ms_per_step, 3),
+                "peak_source": "streaming read bandwidth of the L2 (probe kernel, measured in this run)"}
+    alu = {"bound": "alu", "achieved": round(achieved_tflops, 3), "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+           "frac": round(achieved_tflops / VALU_PEAK_TFLOPS, 4), "flops_per_ray_step": FLOPS_PER_RAY_STEP}
+    # the other rooflines of the tracer: VALU issue (from the profile's
+    # counters, for the same kernel sources) and the gathers of this layout
+    # against the L2 bandwidth and against a gather-only replay of its walks
     valu = None
     if kernel_sources_hash() == TRAFFIC["sources_sha256_16"]:
         r_valu = 256 * 2.4e9 * 64 / TRAFFIC["valu_slots_per_ray_step"]
         valu = {"slots_per_ray_step": TRAFFIC["valu_slots_per_ray_step"], "R_VALU_ray_steps_per_s": r_valu,
                 "frac": round(rate / r_valu, 4)}
-    gathers = None if args.no_probe else l2_gather_roofline(R, torch, model, wl, rate)
+    gathers = l2_gather_roofline(R, torch, model, wl, rate, bw, replay=not args.no_probe)
+    batching = None if args.no_batching else batching_measure(R, torch, freq_stride=8)
     cpu = None if args.no_cpu else cpu_baseline(cor, wl, args.cpu_seconds)
     line = {
         "metric": "ray-steps/s and 512^2 x 8-freq T_b maps/s (plain vs batched); adjoint/fwd ratio",
@@ -706,11 +1022,14 @@ def main():
         "batched": {"ms_per_step": ms_per_step, "ray_steps_per_s": rate, "launch_tuning": tune_info},
         "plain": plain,
         "batched_over_plain": (plain["ms_per_step"] / ms_per_step) if plain else None,
+        "batched_over_plain_c2_subset": batching["batched_workload"]["batched_over_plain"] if batching else None,
         "adjoint_fwd_ratio": adjoint["ratio"] if adjoint else None,
         "adjoint": adjoint,
         "wall_s": wall,
         "roofline": roofline,
+        "alu_roofline": alu,
         "valu_roofline": valu,
+        "batching": batching,
         "l2_gather_roofline": gathers,
         "cpu_baseline": cpu,
     }

@@ -24,10 +24,18 @@
  *    not errors.
  *  - The caller owns every input and output buffer.  The library owns an
  *    rt_model's device copy until rt_model_free, and its own scratch.
- *  - Trace calls on one device share that device's scratch (per-pixel launch
- *    table, work counters, adjoint workspace): calls that could run at the
- *    same time on different streams of one device race.  Issue them on one
- *    stream, or synchronise between them.
+ *  - Library scratch (per-pixel launch table, work counters, path-ray list,
+ *    beam intermediate, adjoint workspace) is kept per device and per stream:
+ *    calls on one stream run in order and share it, calls on different streams
+ *    use their own, so calls on different streams do not race.  Scratch grows
+ *    on demand; an outgrown table is retired, not freed, so that a HIP graph
+ *    that captured a trace call stays valid after later, larger calls (the
+ *    adjoint workspace is freed when outgrown, and rt_trace_adjoint refuses
+ *    graph capture).  A captured graph uses the tables of the stream it was
+ *    captured on: replaying it while another call runs on that stream races.
+ *  - Grid limits (RT_E_CAPACITY): n0 * n1 < 2^24, the packed row length
+ *    (n2 + 1 for spherical grids, n2 for Cartesian) < 2^24, and
+ *    n0 * n1 * (packed row length) <= 2^31 - 1.
  */
 #ifndef RTSUN_H
 #define RTSUN_H
@@ -122,7 +130,12 @@ typedef struct {
 enum {
   RT_USE_MAGNIFICATION = 1u << 0,  /* geometric d ln S/ds term (Eqs. 2-3, 7-12) */
   RT_USE_REFRACTION = 1u << 1,     /* off: straight lines of sight, n taken as 1 (Sec. 3.3) */
-  RT_PREC_ALL_FP32 = 1u << 2,      /* area estimate and transfer in FP32 instead of FP64 */
+  RT_PREC_ALL_FP32 = 1u << 2,      /* everything in FP32: ray state, step increments, grid
+                                      index (cell + FP32 fraction), the area estimate of
+                                      Eqs. 9-11 and the transfer accumulators.  Default
+                                      (no precision flag): model evaluations in FP32,
+                                      state, increments, grid index, area and transfer in
+                                      FP64 */
   RT_SCHED_PLAIN = 1u << 3,        /* one launch per (model, frequency) image instead of
                                       one persistent launch over all of them */
   RT_DETERMINISTIC_GRAD = 1u << 4, /* reserved (rt_trace_adjoint: RT_E_UNSUPPORTED) */
@@ -134,10 +147,16 @@ enum {
                                       ln M of a step = ln(S_{i+1}/S_i), S = |(dr_a x dr_b)
                                       . p/|p||, dr the separations at equal t.  Needs
                                       RT_USE_REFRACTION | RT_USE_MAGNIFICATION
-                                      (RT_E_INVALID_ARG otherwise); mixed precision only
-                                      (RT_E_UNSUPPORTED with RT_PREC_ALL_FP32); always one
+                                      (RT_E_INVALID_ARG otherwise); default precision only
+                                      (RT_E_UNSUPPORTED with RT_PREC_ALL_FP32 or
+                                      RT_PREC_FP32_STEP); always one
                                       launch per image; rt_autotune: RT_E_INVALID_ARG;
                                       rt_trace_adjoint: RT_E_UNSUPPORTED */
+  RT_PREC_FP32_STEP = 1u << 6,     /* FP32 stepping: ray state, step increments and grid
+                                      index in FP32; the area estimate (differences of
+                                      perturbed neighbour rays, Eqs. 9-11) and the optical
+                                      depth / brightness accumulation (Eqs. 2-3, 12) in
+                                      FP64.  RT_PREC_ALL_FP32 takes precedence */
   RT_TEST_NO_ABSORPTION = 1u << 30 /* kappa = 0 (tests of I*S = const, Eq. 1) */
 };
 
@@ -258,10 +277,12 @@ rt_status rt_trace_maps(const rt_model* const* models, int32_t n_models, const d
  * 8 GiB budget (the environment variable RT_ADJOINT_CHECKPOINT_BYTES, read at
  * each call, sets another; at least one tile is taken per batch).  Channel adjoints are accumulated per lane and cell in FP32 and
  * added into an FP64 per-vertex accumulator with atomics, so the last bits can
- * vary between runs.  Mixed precision only: RT_PREC_ALL_FP32,
+ * vary between runs.  Default precision only: RT_PREC_ALL_FP32, RT_PREC_FP32_STEP,
  * RT_DETERMINISTIC_GRAD and RT_TEST_NO_ABSORPTION return RT_E_UNSUPPORTED.  The
- * library keeps a per-device workspace (checkpoints, chunk records,
- * accumulator), grown on demand and kept until the process ends.
+ * library keeps a workspace per device and stream (checkpoints, chunk
+ * records, accumulator), grown on demand and kept until the process ends; a
+ * call issued while `hip_stream` is being captured into a graph returns
+ * RT_E_UNSUPPORTED.
  * Errors: RT_E_INVALID_ARG for NULL or inconsistent arguments, RT_E_CAPACITY,
  * RT_E_OUT_OF_MEMORY, RT_E_DEVICE; nothing is written on a validation error. */
 rt_status rt_trace_adjoint(const rt_model* model, const double* freq_hz, int32_t n_freq,

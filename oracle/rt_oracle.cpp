@@ -221,6 +221,7 @@ struct Result {
   double bouguer_drift;        // max |(|r x p| - L0)| / L0 over accepted steps
   double ham_drift;            // max abs(|p|^2 + X - 1) over accepted steps
   double ln_s_min;             // smallest ln(S/S_0) over the step points (0 at the start)
+  double twin_dexit;           // exit movement of the twin ray [R_sun]; -1 if no twin was traced, +inf if its code differs
   int32_t n_steps, code, flags, _pad;
 };
 
@@ -430,8 +431,8 @@ Sample<S> eval_medium(const Medium& m, const Src& src, const V3<S>& pos, bool wa
       out.grad = {S(0.0), S(0.0), S(m.a0 / m.a2)};
       out.te = S(m.t_const);
       break;
-    case ANALYTIC_LENS:  // n_e = a0 (x^2 + y^2)
-      out.ne = S(m.a0) * (pos.x * pos.x + pos.y * pos.y);
+    case ANALYTIC_LENS:  // n_e = a1 + a0 (x^2 + y^2): a quadratic lens about the z axis on a uniform background
+      out.ne = S(m.a1) + S(m.a0) * (pos.x * pos.x + pos.y * pos.y);
       out.grad = {S(2.0 * m.a0) * pos.x, S(2.0 * m.a0) * pos.y, S(0.0)};
       out.te = S(m.t_const);
       break;
@@ -872,6 +873,7 @@ static void fill_result(const RayOut<double>& ro, Result& r) {
   r.exit_pos[0] = ro.exit_pos.x; r.exit_pos[1] = ro.exit_pos.y; r.exit_pos[2] = ro.exit_pos.z;
   r.lam_last = ro.lam_last; r.n_steps = ro.n_steps; r.code = ro.code; r.flags = ro.flags;
   r.bouguer_drift = ro.bouguer_drift; r.ham_drift = ro.ham_drift; r.ln_s_min = ro.ln_s_min; r._pad = 0;
+  r.twin_dexit = -1.0;
 }
 
 static RayOut<double> trace_any(const Medium& m, const Params& P, double f, const V3<double>& r0,
@@ -883,8 +885,9 @@ static RayOut<double> trace_any(const Medium& m, const Params& P, double f, cons
 
 // Grazing / ill-conditioned classification of a traced image ray.
 static int grazing_flags(const Medium& m, const Params& P, const Image& im, double f, int ju, int iv,
-                         const RayOut<double>& ro) {
+                         const RayOut<double>& ro, double* twin_dexit) {
   int fl = 0;
+  *twin_dexit = -1.0;
   if (ro.code == HIT_INNER) {
     // incidence at the inner sphere: angle between the exit point's radial
     // direction and the final chord, from a re-trace that records the path
@@ -907,7 +910,9 @@ static int grazing_flags(const Medium& m, const Params& P, const Image& im, doub
     Launch T = pixel_launch(im, m.r_max, ju, iv, 1e-6);
     RayOut<double> tw = trace_any(m, P, f, T.r0, T.dir, nullptr, 0, nullptr);
     double dx = tw.exit_pos.x - ro.exit_pos.x, dy = tw.exit_pos.y - ro.exit_pos.y, dz = tw.exit_pos.z - ro.exit_pos.z;
-    if (tw.code != ro.code || std::sqrt(dx * dx + dy * dy + dz * dz) > P.twin_exit_tol) fl |= GRAZING;
+    const double move = std::sqrt(dx * dx + dy * dy + dz * dz);
+    *twin_dexit = (tw.code != ro.code) ? std::numeric_limits<double>::infinity() : move;
+    if (tw.code != ro.code || move > P.twin_exit_tol) fl |= GRAZING;
   }
   return fl;
 }
@@ -972,7 +977,7 @@ int orc_trace_pixels(const Medium* m, const Params* P, const Image* im, double f
     }
     RayOut<double> ro = trace_any(*m, *P, freq, L.r0, L.dir, nullptr, 0, nullptr);
     fill_result(ro, r);
-    r.flags |= grazing_flags(*m, *P, *im, freq, ju, iv, ro);
+    r.flags |= grazing_flags(*m, *P, *im, freq, ju, iv, ro, &r.twin_dexit);
   });
   return 0;
 }

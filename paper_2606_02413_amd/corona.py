@@ -119,6 +119,32 @@ def _random_field(xyz_flat, rng, n_feat, ell, device):
     return out
 
 
+def structured_parts(nr=256, nt=128, nph=256, r_in=1.0, r_max=30.0, seed=0, n_ar=8, n_feat=512, ell=0.1,
+                     device="cpu"):
+    """The seeded pieces of a structured corona (see structured()), float64 over
+    the vertices in C order: ln of the Baumbach-Allen density, the random field
+    g, the unit Gaussian profile G_k of every active region, and the active
+    regions' density factors A_k and peak temperatures T_k."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    xyz = vertex_xyz(nr, nt, nph, r_in, r_max).reshape(-1, 3)
+    r, _, _ = vertex_coords(nr, nt, nph, r_in, r_max)
+    g = _random_field(xyz, rng, n_feat, ell, device)
+    ba = np.broadcast_to(ba_density(r)[:, None, None], (nr, nt, nph)).reshape(-1)
+    prof, dens, temp = [], [], []
+    for _ in range(n_ar):
+        rc = rng.uniform(1.05, 1.2)
+        ctc = rng.uniform(-0.5, 0.5)
+        phc = rng.uniform(-0.5 * math.pi, 0.5 * math.pi)
+        w = rng.uniform(0.05, 0.15)
+        dens.append(rng.uniform(3.0, 8.0))
+        temp.append(rng.uniform(2.0e6, 3.0e6))
+        stc = math.sqrt(1.0 - ctc * ctc)
+        c = np.array([rc * stc * math.cos(phc), rc * stc * math.sin(phc), rc * ctc])
+        d2 = ((xyz - c) ** 2).sum(axis=1)
+        prof.append(np.exp(-d2 / (2.0 * w * w)))
+    return {"ba": ba, "g": g, "G": np.array(prof).reshape(n_ar, -1), "A": np.array(dens), "T": np.array(temp)}
+
+
 def structured(nr=256, nt=128, nph=256, r_in=1.0, r_max=30.0, seed=0, n_ar=8,
                t_bg=1.2e6, n_feat=512, ell=0.1, amp=0.3, device="cpu"):
     """Baumbach-Allen x exp(amp*g) with Gaussian active regions (seeded).
@@ -130,26 +156,14 @@ def structured(nr=256, nt=128, nph=256, r_in=1.0, r_max=30.0, seed=0, n_ar=8,
     A ~ U[3, 8], peak temperature ~ U[2, 3] MK.  With G = exp(-|x - x_c|^2 / 2w^2):
     n_e <- n_e * prod(1 + (A - 1) G);  T = t_bg + max_k (T_k - t_bg) G_k.
     """
-    rng = np.random.Generator(np.random.PCG64(seed))
-    xyz = vertex_xyz(nr, nt, nph, r_in, r_max).reshape(-1, 3)
-    r, _, _ = vertex_coords(nr, nt, nph, r_in, r_max)
-    g = _random_field(xyz, rng, n_feat, ell, device)
-    ne = np.broadcast_to(ba_density(r)[:, None, None], (nr, nt, nph)).reshape(-1) * np.exp(amp * g)
-    te = np.full(xyz.shape[0], t_bg, dtype=np.float64)
-    dte = np.zeros(xyz.shape[0], dtype=np.float64)
-    for _ in range(n_ar):
-        rc = rng.uniform(1.05, 1.2)
-        ctc = rng.uniform(-0.5, 0.5)
-        phc = rng.uniform(-0.5 * math.pi, 0.5 * math.pi)
-        w = rng.uniform(0.05, 0.15)
-        amp_n = rng.uniform(3.0, 8.0)
-        t_ar = rng.uniform(2.0e6, 3.0e6)
-        stc = math.sqrt(1.0 - ctc * ctc)
-        c = np.array([rc * stc * math.cos(phc), rc * stc * math.sin(phc), rc * ctc])
-        d2 = ((xyz - c) ** 2).sum(axis=1)
-        gk = np.exp(-d2 / (2.0 * w * w))
-        ne *= 1.0 + (amp_n - 1.0) * gk
-        dte = np.maximum(dte, (t_ar - t_bg) * gk)
+    p = structured_parts(nr, nt, nph, r_in, r_max, seed, n_ar, n_feat, ell, device)
+    ne = p["ba"] * np.exp(amp * p["g"])
+    te = np.full(ne.shape[0], t_bg, dtype=np.float64)
+    dte = np.zeros(ne.shape[0], dtype=np.float64)
+    for k in range(n_ar):
+        gk = p["G"][k]
+        ne *= 1.0 + (p["A"][k] - 1.0) * gk
+        dte = np.maximum(dte, (p["T"][k] - t_bg) * gk)
     te = te + dte
     return Corona(nr, nt, nph, r_in, r_max,
                   ne.reshape(nr, nt, nph).astype(np.float32),

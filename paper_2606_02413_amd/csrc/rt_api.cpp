@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <cstdlib>
 #include <cstring>
+#include <memory>
 #include <mutex>
 #include <new>
 #include <string>
@@ -64,44 +65,91 @@ rt_status hip_check(hipError_t e, const char* what) {
 
 bool finite3(const double* v) { return std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]); }
 
-// Per-device scratch owned by the library: claim counters of persistent launches
-// (a ring of slots, so consecutive calls do not share counters) and the device
-// copy of a call's path-ray list.
+// Library-owned device tables of the trace calls.
+//
+// A block that a call outgrows is retired, not freed: a HIP graph captured
+// earlier may still launch kernels that read it, so retired blocks stay
+// allocated until the process ends.  Every call rewrites the contents it reads
+// (launch table, start n_e, counters) before reading them, on its own stream.
+struct Block {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+// The tables of one stream.  Calls on one stream run in order and share them;
+// calls on different streams use different tables, so they do not race.
+struct StreamTables {
+  hipStream_t stream = nullptr;
+  unsigned* counters = nullptr;  // kXcds claim counters (persistent trace, adjoint sweep)
+  Block launch;                  // per-pixel start point and grid index, 48 B a pixel
+  Block start_ne;                // n_e at the start point per (model, pixel)
+  Block path_rays;               // device copy of a call's path-ray list
+  Block blur_tmp;                // intermediate maps of the beam convolution
+  Block adj;                     // adjoint workspace (freed when outgrown: the adjoint refuses capture)
+};
+
 struct DeviceScratch {
-  unsigned* counters = nullptr;
-  unsigned next_slot = 0;
-  int32_t* path_rays = nullptr;
-  size_t path_cap = 0;
-  double* start_idx = nullptr;   // per-pixel start grid index, grown on demand
-  size_t start_cap = 0;          // pixels
-  float* start_ne = nullptr;     // per-(model, pixel) n_e at the start point
-  size_t start_ne_cap = 0;
-  void* adj_ws = nullptr;        // adjoint workspace (checkpoints, chunk records, channel adjoints), grown on demand
-  size_t adj_bytes = 0;
-  float* blur_tmp = nullptr;     // intermediate maps of the beam convolution, grown on demand
-  size_t blur_bytes = 0;
   int n_cu = 0;
   rt_tuning tune{RT_ABI_VERSION, 64, 0, kXcds};  // launch tuning of the persistent trace
+  std::vector<std::unique_ptr<StreamTables>> streams;
+  std::vector<Block> retired;
 };
 constexpr long long kAdjMaxCheckpoints = 128;  // per ray; longer rays thin their checkpoints
 constexpr long long kAdjCheckpointBudget = 8ll << 30;  // bytes of per-ray checkpoints per batch of tiles
-constexpr unsigned kCounterSlots = 1024;
 std::mutex g_scratch_mu;
 DeviceScratch g_scratch[64];
 
+
+// Call with g_scratch_mu held.
 rt_status scratch_for(int dev, DeviceScratch** out) {
   if (dev < 0 || dev >= 64) return fail(RT_E_DEVICE, "device index out of range");
   DeviceScratch& s = g_scratch[dev];
-  if (!s.counters) {
-    void* p = nullptr;
-    rt_status st = dev_alloc(&p, sizeof(unsigned) * kXcds * kCounterSlots, "work-queue counters");
-    if (st != RT_OK) return st;
-    s.counters = static_cast<unsigned*>(p);
+  if (s.n_cu == 0) {
     int n = 0;
     if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n < 1) n = 1;
     s.n_cu = n;
   }
   *out = &s;
+  return RT_OK;
+}
+
+// Call with g_scratch_mu held and `dev` current.
+rt_status tables_for(int dev, hipStream_t stream, DeviceScratch** sc_out, StreamTables** out) {
+  DeviceScratch* sc = nullptr;
+  rt_status st = scratch_for(dev, &sc);
+  if (st != RT_OK) return st;
+  *sc_out = sc;
+  for (auto& t : sc->streams)
+    if (t->stream == stream) {
+      *out = t.get();
+      return RT_OK;
+    }
+  std::unique_ptr<StreamTables> t(new (std::nothrow) StreamTables());
+  if (!t) return fail(RT_E_OUT_OF_MEMORY, "host allocation");
+  t->stream = stream;
+  void* p = nullptr;
+  st = dev_alloc(&p, sizeof(unsigned) * kXcds, "work-queue counters");
+  if (st != RT_OK) return st;
+  t->counters = static_cast<unsigned*>(p);
+  *out = t.get();
+  sc->streams.push_back(std::move(t));
+  return RT_OK;
+}
+
+// Grow a block to at least `need` bytes; the outgrown block is retired (kept
+// allocated) unless `can_free`.  Call with g_scratch_mu held.
+rt_status grow(DeviceScratch* sc, Block& b, size_t need, const char* what, bool can_free = false) {
+  if (b.bytes >= need) return RT_OK;
+  if (b.p) {
+    if (can_free) dev_free(b.p, b.bytes);
+    else sc->retired.push_back(b);
+  }
+  b = Block{};
+  void* p = nullptr;
+  rt_status st = dev_alloc(&p, need, what);
+  if (st != RT_OK) return st;
+  b.p = p;
+  b.bytes = need;
   return RT_OK;
 }
 
@@ -138,8 +186,14 @@ rt_status validate_desc(const rt_grid_desc* d) {
   } else {
     return fail(RT_E_INVALID_ARG, "unknown grid kind");
   }
-  const long long n = (long long)d->n0 * d->n1 * d->n2;
-  if (n > (1ll << 31) - 1) return fail(RT_E_CAPACITY, "grid has more than 2^31-1 vertices");
+  // The kernels form a cell's key (a n1 + b) n2p + c with 24-bit multiplies and
+  // keep keys in 32-bit ints: n0 n1 and the packed row length n2p (n2 + 1 on
+  // spherical grids) must stay below 2^24, and n0 n1 n2p below 2^31.
+  const long long n2p = d->kind == RT_GRID_SPHERICAL_LOGR ? (long long)d->n2 + 1 : (long long)d->n2;
+  if ((long long)d->n0 * d->n1 >= (1ll << 24) || n2p >= (1ll << 24))
+    return fail(RT_E_CAPACITY, "grid needs n0*n1 < 2^24 and a packed row length below 2^24");
+  if ((long long)d->n0 * d->n1 * n2p > (1ll << 31) - 1)
+    return fail(RT_E_CAPACITY, "grid has more than 2^31-1 packed vertices");
   return RT_OK;
 }
 
@@ -206,18 +260,11 @@ void free_model_memory(rt_model* m) {
 }
 
 
-unsigned* next_counters(DeviceScratch* sc) {
-  std::lock_guard<std::mutex> lk(g_scratch_mu);
-  const unsigned slot = sc->next_slot++ % kCounterSlots;
-  return sc->counters + size_t(slot) * kXcds;
-}
-
 // Validation of a trace call (host only) and the parts of its launch plan that
 // the forward and the adjoint share: geometry, frequencies, image axes, stepping
 // controls and the per-pixel launch table.
-rt_status prepare_call(const rt_model* const* models, int32_t n_models, const double* freq_hz, int32_t n_freq,
-                       const rt_image_desc* image, const rt_params* params, hipStream_t s, TraceArgs& a,
-                       DeviceScratch** sc_out) {
+rt_status validate_call(const rt_model* const* models, int32_t n_models, const double* freq_hz, int32_t n_freq,
+                        const rt_image_desc* image, const rt_params* params, TraceArgs& a) {
   if (!models || n_models < 1) return fail(RT_E_INVALID_ARG, "need at least one model");
   if (!freq_hz || n_freq < 1) return fail(RT_E_INVALID_ARG, "need at least one frequency");
   if (!image || !params) return fail(RT_E_INVALID_ARG, "image/params is NULL");
@@ -234,13 +281,14 @@ rt_status prepare_call(const rt_model* const* models, int32_t n_models, const do
   if (n_freq > kMaxFreqs) return fail(RT_E_CAPACITY, "more than 128 frequencies in one call");
   const rt_params& P = *params;
   if (P.abi_version != RT_ABI_VERSION) return fail(RT_E_INVALID_ARG, "params->abi_version mismatch");
-  const uint32_t known = RT_USE_MAGNIFICATION | RT_USE_REFRACTION | RT_PREC_ALL_FP32 | RT_SCHED_PLAIN |
-                         RT_DETERMINISTIC_GRAD | RT_CARRIED_TUBE | RT_TEST_NO_ABSORPTION;
+  const uint32_t known = RT_USE_MAGNIFICATION | RT_USE_REFRACTION | RT_PREC_ALL_FP32 | RT_PREC_FP32_STEP |
+                         RT_SCHED_PLAIN | RT_DETERMINISTIC_GRAD | RT_CARRIED_TUBE | RT_TEST_NO_ABSORPTION;
   if (P.flags & ~known) return fail(RT_E_INVALID_ARG, "unknown flag bits");
   if (P.flags & RT_CARRIED_TUBE) {
     if ((P.flags & (RT_USE_REFRACTION | RT_USE_MAGNIFICATION)) != (RT_USE_REFRACTION | RT_USE_MAGNIFICATION))
       return fail(RT_E_INVALID_ARG, "RT_CARRIED_TUBE needs RT_USE_REFRACTION and RT_USE_MAGNIFICATION");
-    if (P.flags & RT_PREC_ALL_FP32) return fail(RT_E_UNSUPPORTED, "RT_CARRIED_TUBE runs in mixed precision only");
+    if (P.flags & (RT_PREC_ALL_FP32 | RT_PREC_FP32_STEP))
+      return fail(RT_E_UNSUPPORTED, "RT_CARRIED_TUBE runs in the default precision only");
   }
   if (!(std::isfinite(P.ds_max) && P.ds_max > 0.0)) return fail(RT_E_INVALID_ARG, "ds_max must be > 0");
   if (!(std::isfinite(P.n_floor) && P.n_floor > 0.0 && P.n_floor <= 1.0)) return fail(RT_E_INVALID_ARG, "n_floor must be in (0, 1]");
@@ -265,31 +313,6 @@ rt_status prepare_call(const rt_model* const* models, int32_t n_models, const do
   const long long total = npx * n_models * n_freq;
   if (total > (1ll << 31) - 1) return fail(RT_E_CAPACITY, "more than 2^31-1 rays in one call");
 
-  rt_status st = hip_check(hipSetDevice(m0->device), "hipSetDevice");
-  if (st != RT_OK) return st;
-  DeviceScratch* sc = nullptr;
-  {
-    std::lock_guard<std::mutex> lk(g_scratch_mu);
-    st = scratch_for(m0->device, &sc);
-    if (st != RT_OK) return st;
-    if (sc->start_cap < size_t(npx)) {
-      dev_free(sc->start_idx, sc->start_cap * 6 * sizeof(double));
-      sc->start_idx = nullptr;
-      sc->start_cap = 0;
-      st = dev_alloc((void**)&sc->start_idx, size_t(npx) * 6 * sizeof(double), "launch table");
-      if (st != RT_OK) return st;
-      sc->start_cap = size_t(npx);
-    }
-    const size_t nne = size_t(npx) * size_t(n_models);
-    if (sc->start_ne_cap < nne) {
-      dev_free(sc->start_ne, sc->start_ne_cap * sizeof(float));
-      sc->start_ne = nullptr;
-      sc->start_ne_cap = 0;
-      st = dev_alloc((void**)&sc->start_ne, nne * sizeof(float), "start n_e table");
-      if (st != RT_OK) return st;
-      sc->start_ne_cap = nne;
-    }
-  }
   a.g = m0->geom;
   for (int k = 0; k < n_models; ++k) a.models[k] = {models[k]->nfg, models[k]->te};
   for (int k = 0; k < n_freq; ++k) {
@@ -314,12 +337,80 @@ rt_status prepare_call(const rt_model* const* models, int32_t n_models, const do
   a.tb_inner = P.tb_inner_K;
   a.tb_sky = P.tb_sky_K;
   a.flags = P.flags;
-  a.launch = sc->start_idx;
-  a.launch_ne = sc->start_ne;
-  st = hip_check(launch_start_index(a, sc->start_idx, sc->start_ne, s), "start index");
+  return RT_OK;
+}
+
+// Bytes of the per-call tables a validated call reads: launch table and start n_e.
+size_t launch_table_bytes(const TraceArgs& a) { return size_t(a.nu) * size_t(a.nv) * 6 * sizeof(double); }
+size_t start_ne_bytes(const TraceArgs& a) { return size_t(a.nu) * size_t(a.nv) * size_t(a.n_models) * sizeof(float); }
+
+// The stream's tables for a validated call, grown to its size, and the launch
+// table and start n_e written on the stream.
+rt_status prepare_call(const rt_model* const* models, int32_t n_models, const double* freq_hz, int32_t n_freq,
+                       const rt_image_desc* image, const rt_params* params, hipStream_t s, TraceArgs& a,
+                       DeviceScratch** sc_out, StreamTables** tb_out) {
+  rt_status st = validate_call(models, n_models, freq_hz, n_freq, image, params, a);
+  if (st != RT_OK) return st;
+  const int dev = models[0]->device;
+  st = hip_check(hipSetDevice(dev), "hipSetDevice");
+  if (st != RT_OK) return st;
+  DeviceScratch* sc = nullptr;
+  StreamTables* tb = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    st = tables_for(dev, s, &sc, &tb);
+    if (st == RT_OK) st = grow(sc, tb->launch, launch_table_bytes(a), "launch table");
+    if (st == RT_OK) st = grow(sc, tb->start_ne, start_ne_bytes(a), "start n_e table");
+    if (st != RT_OK) return st;
+    a.launch = static_cast<const double*>(tb->launch.p);
+    a.launch_ne = static_cast<const float*>(tb->start_ne.p);
+  }
+  st = hip_check(launch_start_index(a, static_cast<double*>(tb->launch.p), static_cast<float*>(tb->start_ne.p), s),
+                 "start index");
   if (st != RT_OK) return st;
   *sc_out = sc;
+  *tb_out = tb;
   return RT_OK;
+}
+
+// Enqueue the trace kernels of a call whose TraceArgs are complete except for
+// the claim counters: one plain launch per image, or one persistent launch.
+rt_status enqueue_trace(TraceArgs& a, const rt_params& P, int n_cu, const rt_tuning& tune, unsigned* counters,
+                        hipStream_t s) {
+  rt_status st = RT_OK;
+  const int prec = precision_of(P.flags);
+  if (P.flags & (RT_SCHED_PLAIN | RT_CARRIED_TUBE)) {
+    const int waves = a.tiles_per_image;
+    const int blocks = (waves + 3) / 4;
+    for (int mi = 0; mi < a.n_models; ++mi)
+      for (int fi = 0; fi < a.n_freq; ++fi) {
+        a.image0 = mi * a.n_freq + fi;
+        st = hip_check(launch_trace(a, true, prec, blocks, s), "trace launch");
+        if (st != RT_OK) return st;
+      }
+    return RT_OK;
+  }
+  a.counters = counters;
+  a.refill_min_idle = tune.refill_min_idle;
+  const int bands = tune.xcd_bands;
+  a.n_bands = bands;
+  const int n_images = a.n_models * a.n_freq;
+  a.range_lo[0] = 0;
+  for (int x = 0; x < kXcds; ++x) {
+    // rows of band x (bands = 1: every row in band 0, the others empty)
+    const int row0 = x < bands ? (x * a.tiles_v) / bands : a.tiles_v;
+    const int row1 = x < bands ? ((x + 1) * a.tiles_v) / bands : a.tiles_v;
+    a.range_lo[x + 1] = a.range_lo[x] + (row1 - row0) * a.tiles_u * n_images;
+  }
+  st = hip_check(launch_fill_u32(a.counters, 0u, kXcds, s), "counter fill");
+  if (st != RT_OK) return st;
+  int per_cu = persistent_blocks_per_cu(prec, a.g.kind, P.flags);
+  if (tune.blocks_per_cu > 0 && tune.blocks_per_cu < per_cu) per_cu = tune.blocks_per_cu;
+  long long blocks = (long long)n_cu * per_cu;
+  const long long max_useful = ((long long)a.range_lo[kXcds] + 3) / 4;
+  if (blocks > max_useful) blocks = max_useful;
+  if (blocks < 1) blocks = 1;
+  return hip_check(launch_trace(a, false, prec, int(blocks), s), "persistent trace launch");
 }
 
 }  // namespace
@@ -468,7 +559,8 @@ rt_status rt_trace_maps(const rt_model* const* models, int32_t n_models, const d
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
     TraceArgs a{};
     DeviceScratch* sc = nullptr;
-    rt_status st = prepare_call(models, n_models, freq_hz, n_freq, image, params, s, a, &sc);
+    StreamTables* tb = nullptr;
+    rt_status st = prepare_call(models, n_models, freq_hz, n_freq, image, params, s, a, &sc, &tb);
     if (st != RT_OK) return st;
     const long long total = (long long)a.nu * a.nv * n_models * n_freq;
     if (n_path_rays < 0) return fail(RT_E_INVALID_ARG, "n_path_rays < 0");
@@ -481,20 +573,14 @@ rt_status rt_trace_maps(const rt_model* const* models, int32_t n_models, const d
       }
       {
         std::lock_guard<std::mutex> lk(g_scratch_mu);
-        if (sc->path_cap < size_t(n_path_rays)) {
-          dev_free(sc->path_rays, sc->path_cap * sizeof(int32_t));
-          sc->path_rays = nullptr;
-          sc->path_cap = 0;
-          st = dev_alloc((void**)&sc->path_rays, size_t(n_path_rays) * sizeof(int32_t), "path rays");
-          if (st != RT_OK) return st;
-          sc->path_cap = size_t(n_path_rays);
-        }
+        st = grow(sc, tb->path_rays, size_t(n_path_rays) * sizeof(int32_t), "path rays");
+        if (st != RT_OK) return st;
       }
-      st = hip_check(hipMemcpyAsync(sc->path_rays, path_rays, size_t(n_path_rays) * sizeof(int32_t),
+      st = hip_check(hipMemcpyAsync(tb->path_rays.p, path_rays, size_t(n_path_rays) * sizeof(int32_t),
                                     hipMemcpyHostToDevice, s), "copy path rays");
       if (st == RT_OK) st = hip_check(hipStreamSynchronize(s), "path rays sync");
       if (st != RT_OK) return st;
-      a.path_rays = sc->path_rays;
+      a.path_rays = static_cast<const int32_t*>(tb->path_rays.p);
       a.n_path = n_path_rays;
       a.path_cap = path_capacity;
       a.path_out = path_out;
@@ -507,47 +593,12 @@ rt_status rt_trace_maps(const rt_model* const* models, int32_t n_models, const d
       st = hip_check(launch_fill_u32(reinterpret_cast<unsigned*>(stats_out), 0u, sizeof(rt_trace_stats) / 4, s), "stats fill");
       if (st != RT_OK) return st;
     }
-    const rt_params& P = *params;
-    const bool mixed = (P.flags & RT_PREC_ALL_FP32) == 0;
-    if (P.flags & (RT_SCHED_PLAIN | RT_CARRIED_TUBE)) {
-      const int waves = a.tiles_per_image;
-      const int blocks = (waves + 3) / 4;
-      for (int mi = 0; mi < n_models; ++mi)
-        for (int fi = 0; fi < n_freq; ++fi) {
-          a.image0 = mi * n_freq + fi;
-          st = hip_check(launch_trace(a, true, mixed, blocks, s), "trace launch");
-          if (st != RT_OK) return st;
-        }
-    } else {
-      rt_tuning tune;
-      {
-        std::lock_guard<std::mutex> lk(g_scratch_mu);
-        tune = sc->tune;
-      }
-      a.counters = next_counters(sc);
-      a.refill_min_idle = tune.refill_min_idle;
-      const int bands = tune.xcd_bands;
-      a.n_bands = bands;
-      const int n_images = n_models * n_freq;
-      a.range_lo[0] = 0;
-      for (int x = 0; x < kXcds; ++x) {
-        // rows of band x (bands = 1: every row in band 0, the others empty)
-        const int row0 = x < bands ? (x * a.tiles_v) / bands : a.tiles_v;
-        const int row1 = x < bands ? ((x + 1) * a.tiles_v) / bands : a.tiles_v;
-        a.range_lo[x + 1] = a.range_lo[x] + (row1 - row0) * a.tiles_u * n_images;
-      }
-      st = hip_check(launch_fill_u32(a.counters, 0u, kXcds, s), "counter fill");
-      if (st != RT_OK) return st;
-      int per_cu = persistent_blocks_per_cu(mixed, a.g.kind, P.flags);
-      if (tune.blocks_per_cu > 0 && tune.blocks_per_cu < per_cu) per_cu = tune.blocks_per_cu;
-      long long blocks = (long long)sc->n_cu * per_cu;
-      const long long max_useful = ((long long)a.range_lo[kXcds] + 3) / 4;
-      if (blocks > max_useful) blocks = max_useful;
-      if (blocks < 1) blocks = 1;
-      st = hip_check(launch_trace(a, false, mixed, int(blocks), s), "persistent trace launch");
-      if (st != RT_OK) return st;
+    rt_tuning tune;
+    {
+      std::lock_guard<std::mutex> lk(g_scratch_mu);
+      tune = sc->tune;
     }
-    return RT_OK;
+    return enqueue_trace(a, *params, sc->n_cu, tune, tb->counters, s);
   } catch (...) {
     return fail(RT_E_INTERNAL, "unexpected exception");
   }
@@ -640,8 +691,7 @@ rt_status rt_autotune(const rt_model* const* models, int32_t n_models, const dou
     if (st == RT_OK) st = hip_check(hipEventCreate(&e0), "event");
     if (st == RT_OK) st = hip_check(hipEventCreate(&e1), "event");
     if (st != RT_OK) { cleanup(); return st; }
-    const bool mixed = (params->flags & RT_PREC_ALL_FP32) == 0;
-    const int max_per_cu = persistent_blocks_per_cu(mixed, models[0]->geom.kind, params->flags);
+    const int max_per_cu = persistent_blocks_per_cu(precision_of(params->flags), models[0]->geom.kind, params->flags);
     std::vector<rt_tuning> cand;
     rt_tuning d;
     rt_tuning_default(&d);
@@ -747,17 +797,11 @@ rt_status rt_beam_convolve(const float* maps_in, float* maps_out, int32_t n_maps
     {
       std::lock_guard<std::mutex> lk(g_scratch_mu);
       DeviceScratch* sc = nullptr;
-      st = scratch_for(dev, &sc);
+      StreamTables* tb = nullptr;
+      st = tables_for(dev, s, &sc, &tb);
+      if (st == RT_OK) st = grow(sc, tb->blur_tmp, bytes, "beam scratch");
       if (st != RT_OK) return st;
-      if (sc->blur_bytes < bytes) {
-        dev_free(sc->blur_tmp, sc->blur_bytes);
-        sc->blur_tmp = nullptr;
-        sc->blur_bytes = 0;
-        st = dev_alloc((void**)&sc->blur_tmp, bytes, "beam scratch");
-        if (st != RT_OK) return st;
-        sc->blur_bytes = bytes;
-      }
-      tmp = sc->blur_tmp;
+      tmp = static_cast<float*>(tb->blur_tmp.p);
     }
     return hip_check(launch_blur(b, maps_in, tmp, maps_out, s), "beam convolution");
   } catch (...) {
@@ -900,8 +944,8 @@ rt_status rt_trace_adjoint(const rt_model* model, const double* freq_hz, int32_t
     if (!model) return fail(RT_E_INVALID_ARG, "model is NULL");
     if (!weights || !loss_out || !grad_ln_ne || !grad_ln_te)
       return fail(RT_E_INVALID_ARG, "weights, loss_out, grad_ln_ne and grad_ln_te must not be NULL");
-    if (params && (params->flags & RT_PREC_ALL_FP32))
-      return fail(RT_E_UNSUPPORTED, "the adjoint runs in mixed precision only (RT_PREC_ALL_FP32 is not supported)");
+    if (params && (params->flags & (RT_PREC_ALL_FP32 | RT_PREC_FP32_STEP)))
+      return fail(RT_E_UNSUPPORTED, "the adjoint runs in the default precision only");
     if (params && (params->flags & RT_TEST_NO_ABSORPTION))
       return fail(RT_E_UNSUPPORTED, "RT_TEST_NO_ABSORPTION is a forward-only test mode");
     if (params && (params->flags & RT_DETERMINISTIC_GRAD))
@@ -910,10 +954,18 @@ rt_status rt_trace_adjoint(const rt_model* model, const double* freq_hz, int32_t
       return fail(RT_E_UNSUPPORTED, "the adjoint differentiates the step-wise tube estimate only");
     if (params && params->checkpoint_every < 0) return fail(RT_E_INVALID_ARG, "checkpoint_every must be >= 0");
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    // The workspace is sized per call and may be reallocated: a captured graph
+    // would keep a pointer to freed memory, so capture is refused.
+    hipStreamCaptureStatus cap_status = hipStreamCaptureStatusNone;
+    rt_status st = hip_check(hipStreamIsCapturing(s, &cap_status), "hipStreamIsCapturing");
+    if (st != RT_OK) return st;
+    if (cap_status != hipStreamCaptureStatusNone)
+      return fail(RT_E_UNSUPPORTED, "rt_trace_adjoint cannot be captured in a graph");
     TraceArgs a{};
     DeviceScratch* sc = nullptr;
+    StreamTables* tbl = nullptr;
     const rt_model* models[1] = {model};
-    rt_status st = prepare_call(models, 1, freq_hz, n_freq, image, params, s, a, &sc);
+    st = prepare_call(models, 1, freq_hz, n_freq, image, params, s, a, &sc, &tbl);
     if (st != RT_OK) return st;
     const rt_params& P = *params;
     const long long npx = (long long)a.nu * a.nv;
@@ -947,15 +999,9 @@ rt_status rt_trace_adjoint(const rt_model* model, const double* freq_hz, int32_t
     char* ws = nullptr;
     {
       std::lock_guard<std::mutex> lk(g_scratch_mu);
-      if (sc->adj_bytes < need) {
-        dev_free(sc->adj_ws, sc->adj_bytes);
-        sc->adj_ws = nullptr;
-        sc->adj_bytes = 0;
-        st = dev_alloc((void**)&sc->adj_ws, need, "adjoint workspace");
-        if (st != RT_OK) return st;
-        sc->adj_bytes = need;
-      }
-      ws = static_cast<char*>(sc->adj_ws);
+      st = grow(sc, tbl->adj, need, "adjoint workspace", /*can_free=*/true);
+      if (st != RT_OK) return st;
+      ws = static_cast<char*>(tbl->adj.p);
     }
     AdjointArgs aa{};
     size_t off = 0;
@@ -980,7 +1026,7 @@ rt_status rt_trace_adjoint(const rt_model* model, const double* freq_hz, int32_t
       aa.tile0 = t0;
       aa.n_tiles = int(std::min<long long>(batch, n_tiles - t0));
       aa.n_rays = aa.n_tiles * kWaveLanes;
-      aa.counter = next_counters(sc);
+      aa.counter = tbl->counters;
       st = hip_check(launch_fill_u32(aa.counter, 0u, 1, s), "counter fill");
       if (st == RT_OK) st = hip_check(launch_adjoint_forward(aa, s), "adjoint forward launch");
       if (st == RT_OK) st = hip_check(launch_adjoint(aa, int(blocks), s), "adjoint launch");

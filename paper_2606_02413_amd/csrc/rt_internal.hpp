@@ -112,9 +112,13 @@ hipError_t launch_pack(const DevGeom& g, const float* ne, const float* te, float
 hipError_t launch_validate(const float* ne, const float* te, long long n, int* bad, hipStream_t s);
 hipError_t launch_fill_u32(unsigned* p, unsigned val, long long n, hipStream_t s);
 hipError_t launch_count_diff(const unsigned* a, const unsigned* b, long long n, unsigned* count, hipStream_t s);
-hipError_t launch_trace(const TraceArgs& a, bool plain, bool mixed, int grid_blocks, hipStream_t s);
+// prec: kPrecDefault, kPrecFp32Step or kPrecFp32 (rt_trace.hpp), from precision_of(flags)
+hipError_t launch_trace(const TraceArgs& a, bool plain, int prec, int grid_blocks, hipStream_t s);
 hipError_t launch_start_index(const TraceArgs& a, double* out, float* ne_out, hipStream_t s);
-int persistent_blocks_per_cu(bool mixed, int kind, uint32_t flags);
+int persistent_blocks_per_cu(int prec, int kind, uint32_t flags);
+inline int precision_of(uint32_t flags) {
+  return (flags & RT_PREC_ALL_FP32) ? 2 : (flags & RT_PREC_FP32_STEP) ? 1 : 0;
+}
 
 // Launchers (rt_adjoint.hip).
 hipError_t launch_adjoint_forward(const AdjointArgs& a, hipStream_t s);

@@ -159,7 +159,7 @@ __device__ __forceinline__ int xcd_remap(int bid, int nblocks) {
 // MODE kModeCarried: the ray tube is carried along the whole ray by two
 // neighbour rays (launched across the initial direction) instead of being
 // retraced at every step.
-template <bool MIXED, int KIND, int MODE = kModeFlags>
+template <int PREC, int KIND, int MODE = kModeFlags>
 __global__ __launch_bounds__(256, MODE == kModeCarried ? 1 : 2) void k_trace_plain(TraceArgs a) {
   __shared__ float4 lds_c[4][8][kWaveLanes];
   __shared__ float lds_t[4][8][kWaveLanes];
@@ -170,7 +170,7 @@ __global__ __launch_bounds__(256, MODE == kModeCarried ? 1 : 2) void k_trace_pla
   const int j = tx * kTile + (lane & 7), i = ty * kTile + (lane >> 3);
   LaneStats st{};
   if (i < a.nv && j < a.nu) {
-    RayState R;
+    typename StateOf<PREC>::type R;
     CellCache C;
     C.key = -1;
     C.c = &lds_c[wave][0][lane];
@@ -179,7 +179,7 @@ __global__ __launch_bounds__(256, MODE == kModeCarried ? 1 : 2) void k_trace_pla
       if constexpr (MODE == kModeCarried) init_tube<KIND>(a, R, C);
       int code;
       do {
-        code = ray_step<MIXED, KIND, MODE>(a, R, C);
+        code = ray_step<PREC != kPrecFp32, KIND, MODE>(a, R, C);
       } while (code == kRunning);
       finish_ray(a, R);
       lane_stats_add(st, R.n, code);
@@ -214,7 +214,7 @@ __device__ __forceinline__ int tile_slot_ray(const TraceArgs& a, int t, int slot
   return i * a.nu + j;
 }
 
-template <bool MIXED, int KIND, int MODE = kModeFlags>
+template <int PREC, int KIND, int MODE = kModeFlags>
 __global__ __launch_bounds__(256, 2) void k_trace_persistent(TraceArgs a) {
   __shared__ float4 lds_c[4][8][kWaveLanes];
   __shared__ float lds_t[4][8][kWaveLanes];
@@ -223,7 +223,7 @@ __global__ __launch_bounds__(256, 2) void k_trace_persistent(TraceArgs a) {
   unsigned exhausted = 0;
   int pool_left = 0, cur_tile = -1;
   bool active = false;
-  RayState R;
+  typename StateOf<PREC>::type R;
   CellCache C;
   C.key = -1;
   C.c = &lds_c[wave][0][lane];
@@ -273,7 +273,7 @@ __global__ __launch_bounds__(256, 2) void k_trace_persistent(TraceArgs a) {
     if (__ballot(active) == 0ull) break;
     int done = kRunning;
     if (active) {
-      const int code = ray_step<MIXED, KIND, MODE>(a, R, C);
+      const int code = ray_step<PREC != kPrecFp32, KIND, MODE>(a, R, C);
       if (code != kRunning) {
         finish_ray(a, R);
         active = false;
@@ -345,76 +345,66 @@ hipError_t launch_fill_u32(unsigned* p, unsigned val, long long n, hipStream_t s
 }
 
 // The two reduced tracing modes (line of sight; refraction without the tube
-// term) are fixed at compile time for the mixed-precision kernels: without the
-// perturbed retraces the step needs far fewer registers and these kernels run
-// at 3-4 waves per SIMD.  The full method keeps the mode in the call's flags
-// (its compile-time instance spills more and is slower: 993 ms against
-// 979 ms on the structured stack), and so does the all-FP32 variant.
-template <bool MIXED>
-static int launch_mode(uint32_t flags) {
-  if (!MIXED) return kModeFlags;
+// term) are fixed at compile time for the default-precision kernels: without
+// the perturbed retraces the step needs far fewer registers and these kernels
+// run at 3-4 waves per SIMD.  The full method keeps the mode in the call's flags
+// (its compile-time instance spills more and is slower: 993 ms against 979 ms
+// on the structured stack), and so do the FP32-stepping and all-FP32 variants.
+static int launch_mode(int prec, uint32_t flags) {
+  if (prec != kPrecDefault) return kModeFlags;
   if (!(flags & RT_USE_REFRACTION)) return kModeLos;
   return (flags & RT_USE_MAGNIFICATION) ? kModeFlags : kModeNoMag;
 }
 
-template <bool MIXED, int KIND, int MODE>
+template <int PREC, int KIND, int MODE>
 static hipError_t launch_in_mode(const TraceArgs& a, bool plain, int blocks, hipStream_t s) {
-  if (plain) hipLaunchKernelGGL((k_trace_plain<MIXED, KIND, MODE>), dim3(blocks), dim3(256), 0, s, a);
-  else hipLaunchKernelGGL((k_trace_persistent<MIXED, KIND, MODE>), dim3(blocks), dim3(256), 0, s, a);
+  if (plain) hipLaunchKernelGGL((k_trace_plain<PREC, KIND, MODE>), dim3(blocks), dim3(256), 0, s, a);
+  else hipLaunchKernelGGL((k_trace_persistent<PREC, KIND, MODE>), dim3(blocks), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
-template <bool MIXED, int KIND>
-static hipError_t launch_one(const TraceArgs& a, bool plain, int blocks, hipStream_t s) {
+template <int KIND>
+static hipError_t launch_kind(const TraceArgs& a, bool plain, int prec, int blocks, hipStream_t s) {
   if (a.flags & RT_CARRIED_TUBE) {
-    // carried tubes: mixed precision, one launch per image
-    if (!MIXED || !plain) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_trace_plain<true, KIND, kModeCarried>), dim3(blocks), dim3(256), 0, s, a);
+    // carried tubes: default precision, one launch per image
+    if (prec != kPrecDefault || !plain) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_trace_plain<kPrecDefault, KIND, kModeCarried>), dim3(blocks), dim3(256), 0, s, a);
     return hipGetLastError();
   }
-  if constexpr (!MIXED) {
-    return launch_in_mode<false, KIND, kModeFlags>(a, plain, blocks, s);
-  } else {
-    switch (launch_mode<true>(a.flags)) {
-      case kModeLos: return launch_in_mode<true, KIND, kModeLos>(a, plain, blocks, s);
-      case kModeNoMag: return launch_in_mode<true, KIND, kModeNoMag>(a, plain, blocks, s);
-      default: return launch_in_mode<true, KIND, kModeFlags>(a, plain, blocks, s);
-    }
+  if (prec == kPrecFp32) return launch_in_mode<kPrecFp32, KIND, kModeFlags>(a, plain, blocks, s);
+  if (prec == kPrecFp32Step) return launch_in_mode<kPrecFp32Step, KIND, kModeFlags>(a, plain, blocks, s);
+  switch (launch_mode(prec, a.flags)) {
+    case kModeLos: return launch_in_mode<kPrecDefault, KIND, kModeLos>(a, plain, blocks, s);
+    case kModeNoMag: return launch_in_mode<kPrecDefault, KIND, kModeNoMag>(a, plain, blocks, s);
+    default: return launch_in_mode<kPrecDefault, KIND, kModeFlags>(a, plain, blocks, s);
   }
 }
 
-hipError_t launch_trace(const TraceArgs& a, bool plain, bool mixed, int blocks, hipStream_t s) {
-  const bool sph = a.g.kind == RT_GRID_SPHERICAL_LOGR;
-  if (mixed) return sph ? launch_one<true, RT_GRID_SPHERICAL_LOGR>(a, plain, blocks, s)
-                        : launch_one<true, RT_GRID_CARTESIAN>(a, plain, blocks, s);
-  return sph ? launch_one<false, RT_GRID_SPHERICAL_LOGR>(a, plain, blocks, s)
-             : launch_one<false, RT_GRID_CARTESIAN>(a, plain, blocks, s);
+hipError_t launch_trace(const TraceArgs& a, bool plain, int prec, int blocks, hipStream_t s) {
+  if (a.g.kind == RT_GRID_SPHERICAL_LOGR) return launch_kind<RT_GRID_SPHERICAL_LOGR>(a, plain, prec, blocks, s);
+  return launch_kind<RT_GRID_CARTESIAN>(a, plain, prec, blocks, s);
 }
 
-template <bool MIXED, int KIND, int MODE>
+template <int PREC, int KIND, int MODE>
 static hipError_t occupancy_of(int* n) {
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, k_trace_persistent<MIXED, KIND, MODE>, 256, 0);
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, k_trace_persistent<PREC, KIND, MODE>, 256, 0);
 }
 
 template <int KIND>
-static hipError_t occupancy_mixed(int* n, uint32_t flags) {
-  switch (launch_mode<true>(flags)) {
-    case kModeLos: return occupancy_of<true, KIND, kModeLos>(n);
-    case kModeNoMag: return occupancy_of<true, KIND, kModeNoMag>(n);
-    default: return occupancy_of<true, KIND, kModeFlags>(n);
+static hipError_t occupancy_kind(int* n, int prec, uint32_t flags) {
+  if (prec == kPrecFp32) return occupancy_of<kPrecFp32, KIND, kModeFlags>(n);
+  if (prec == kPrecFp32Step) return occupancy_of<kPrecFp32Step, KIND, kModeFlags>(n);
+  switch (launch_mode(prec, flags)) {
+    case kModeLos: return occupancy_of<kPrecDefault, KIND, kModeLos>(n);
+    case kModeNoMag: return occupancy_of<kPrecDefault, KIND, kModeNoMag>(n);
+    default: return occupancy_of<kPrecDefault, KIND, kModeFlags>(n);
   }
 }
 
-int persistent_blocks_per_cu(bool mixed, int kind, uint32_t flags) {
+int persistent_blocks_per_cu(int prec, int kind, uint32_t flags) {
   int n = 0;
-  hipError_t e;
-  const bool sph = kind == RT_GRID_SPHERICAL_LOGR;
-  if (mixed) {
-    e = sph ? occupancy_mixed<RT_GRID_SPHERICAL_LOGR>(&n, flags) : occupancy_mixed<RT_GRID_CARTESIAN>(&n, flags);
-  } else {
-    e = sph ? occupancy_of<false, RT_GRID_SPHERICAL_LOGR, kModeFlags>(&n)
-            : occupancy_of<false, RT_GRID_CARTESIAN, kModeFlags>(&n);
-  }
+  const hipError_t e = kind == RT_GRID_SPHERICAL_LOGR ? occupancy_kind<RT_GRID_SPHERICAL_LOGR>(&n, prec, flags)
+                                                      : occupancy_kind<RT_GRID_CARTESIAN>(&n, prec, flags);
   if (e != hipSuccess || n < 1) n = 1;
   return n;
 }

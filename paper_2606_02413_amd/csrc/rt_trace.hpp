@@ -12,10 +12,16 @@
 //   logarithm of Dulk (1985).
 //
 // Precision: every evaluation of the model (position offsets, coordinates,
-// trilinear gathers, forces) is FP32.  The ray state r_i, p_i and the grid index
-// of r_i accumulate in FP64; the ray-tube area and the optical depth / brightness
-// accumulators are FP64 (FP32 in the all-FP32 variant).
+// trilinear gathers, forces) is FP32.  Three variants of the rest:
+//   default       the ray state r_i, p_i, the step increments and the grid index
+//                 of r_i in FP64; ray-tube area and the optical depth /
+//                 brightness accumulators in FP64;
+//   FP32 stepping the ray state, increments and grid index (integer cell + FP32
+//                 fraction) in FP32; area and accumulators in FP64;
+//   all-FP32      everything in FP32.
 #pragma once
+
+#include <type_traits>
 
 #include "rt_internal.hpp"
 
@@ -29,6 +35,9 @@ enum : int { kRunning = 0, kExit = 1, kHit = 2, kMiss = 3, kMaxSteps = 4, kNonfi
 
 template <bool MIXED> struct RealOf { using T = double; };
 template <> struct RealOf<false> { using T = float; };
+
+// Precision variants of the trace kernels.
+enum : int { kPrecDefault = 0, kPrecFp32Step = 1, kPrecFp32 = 2 };
 
 // ---------------------------------------------------------------------------
 // Small math kernels with few constants (so that nothing large is kept live
@@ -140,6 +149,8 @@ __device__ __forceinline__ double rsqrt_r(double x) { return rsqrt64(x); }
 __device__ __forceinline__ float rsqrt_r(float x) { return rsqrtf(x); }
 __device__ __forceinline__ double rcp_r(double x) { return rcp64(x); }
 __device__ __forceinline__ float rcp_r(float x) { return rcpf(x); }
+__device__ __forceinline__ double sqrt_r(double x) { return sqrt64(x); }
+__device__ __forceinline__ float sqrt_r(float x) { return x > 0.0f ? sqrt_fast(x) : 0.0f; }
 
 // FP64 series for the per-step index increments, valid for small arguments
 // only (|w|, |t| <= 1/32): three shared coefficients keep the loop free of
@@ -416,13 +427,26 @@ __device__ __forceinline__ void eval_value(const DevGeom& g, const float4* nfg, 
 // ---------------------------------------------------------------------------
 // Ray state and its life cycle.
 // ---------------------------------------------------------------------------
-struct RayState {
-  double rx, ry, rz;        // position r_i (on termination: the end point)
-  double px, py, pz;        // normalised wavevector p_i
-  double b0, b1, b2;        // continuous grid index of r_i
-  double A;                 // composite: emitted part (front to back)
-  double lam_tot;           // optical depth of the segments so far, geometric term included
-  double tau, lns, s_arc;
+// Grid index of r_i: the continuous index in FP64 (FP64 state), or the integer
+// cell and the FP32 fraction in [0, 1) along each axis (FP32 state).
+template <class S> struct GridIndexOf {
+  double b0, b1, b2;
+};
+template <> struct GridIndexOf<float> {
+  int i0, i1, i2;
+  float fr0, fr1, fr2;
+};
+
+// S: position, wavevector and their step increments; Real: the ray-tube area
+// and the transfer accumulators.
+template <class S, class Real>
+struct RayStateT : GridIndexOf<S> {
+  S rx, ry, rz;             // position r_i (on termination: the end point)
+  S px, py, pz;             // normalised wavevector p_i
+  Real A;                   // composite: emitted part (front to back)
+  Real lam_tot;             // optical depth of the segments so far, geometric term included
+  Real tau, lns;
+  S s_arc;
   double cfd;               // -1/2 Xf in FP64, Xf = (8.98e3 / f)^2
   const float4* nfg;        // this ray's model
   const float* te;
@@ -437,6 +461,11 @@ struct RayState {
   double nb_r[2][3], nb_p[2][3];
   double tube_ln_s;
 };
+using RayState = RayStateT<double, double>;
+
+template <int PREC> struct StateOf { using type = RayStateT<double, double>; };
+template <> struct StateOf<kPrecFp32Step> { using type = RayStateT<float, double>; };
+template <> struct StateOf<kPrecFp32> { using type = RayStateT<float, float>; };
 
 // Chord-sphere crossing: root in [0, 1] of |o + lam d|^2 = R^2 (outward: larger root).
 template <class Real>
@@ -490,22 +519,24 @@ __device__ __forceinline__ void write_miss(const TraceArgs& a, int id, double b,
   }
 }
 
-template <int KIND>
-__device__ __forceinline__ void make_origin(const RayState& R, StepOrigin& O) {
-  const double rho2 = R.rx * R.rx + R.ry * R.ry;
-  const double r2 = rho2 + R.rz * R.rz;
-  double rho;
+template <int KIND, class S, class Real>
+__device__ __forceinline__ void make_origin(const RayStateT<S, Real>& R, StepOrigin& O) {
+  const S rho2 = R.rx * R.rx + R.ry * R.ry;
+  const S r2 = rho2 + R.rz * R.rz;
   O.x = float(R.rx); O.y = float(R.ry); O.z = float(R.rz);
   if constexpr (KIND == RT_GRID_SPHERICAL_LOGR) {
-    rho = sqrt64(rho2);
-    O.r2 = float(r2); O.inv_r2 = float(rcp64(r2)); O.rho2 = float(rho2); O.rho = float(rho);
+    O.r2 = float(r2); O.inv_r2 = float(rcp_r(r2)); O.rho2 = float(rho2); O.rho = float(sqrt_r(rho2));
   } else {
-    rho = 0.0;
     O.r2 = 0.f; O.inv_r2 = 0.f; O.rho2 = 0.f; O.rho = 0.f;
   }
-  split_index(R.b0, O.i0, O.f0);
-  split_index(R.b1, O.i1, O.f1);
-  split_index(R.b2, O.i2, O.f2);
+  if constexpr (std::is_same<S, double>::value) {
+    split_index(R.b0, O.i0, O.f0);
+    split_index(R.b1, O.i1, O.f1);
+    split_index(R.b2, O.i2, O.f2);
+  } else {
+    O.i0 = R.i0; O.i1 = R.i1; O.i2 = R.i2;
+    O.f0 = R.fr0; O.f1 = R.fr1; O.f2 = R.fr2;
+  }
 }
 
 // Advance the origin's grid index by the step increment d (FP64 small-offset
@@ -548,6 +579,51 @@ __device__ __forceinline__ void index_advance(const DevGeom& g, RayState& R, dou
   }
 }
 
+// FP32 index: add an increment to (cell, fraction) and bring the fraction back
+// to [0, 1).
+__device__ __forceinline__ void advance_cell(int& i, float& f, float d) {
+  float x = f + d;
+  float k = floorf(x);
+  if (!(k >= -1.0e9f && k <= 1.0e9f)) k = 0.0f;  // NaN guard (the step is then non-finite)
+  f = x - k;
+  i += int(k);
+}
+
+// The same advance for FP32 state, all in FP32: the increments of (ln r, theta,
+// phi) from r_i to r_i + d by the small-offset formulas of `locate` (they hold
+// for any increment: log1p and the signed angles fall back to their general
+// forms), the periodic axis wrapped back into [0, n2).
+template <int KIND, class Real>
+__device__ __forceinline__ void index_advance(const DevGeom& g, RayStateT<float, Real>& R, float dx, float dy,
+                                              float dz) {
+  float d0, d1, d2;
+  if constexpr (KIND == RT_GRID_SPHERICAL_LOGR) {
+    const float X = R.rx, Y = R.ry, Z = R.rz;  // old origin
+    const float rho2 = X * X + Y * Y, r2 = rho2 + Z * Z, rho = sqrt_r(rho2);
+    const float rd = X * dx + Y * dy;
+    const float dd = dx * dx + dy * dy;
+    const float c = 2.0f * (rd + Z * dz) + (dd + dz * dz);
+    d0 = 0.5f * log1p_inc(c * rcpf(r2)) * g.inv_dl;
+    d2 = atan2_inc(X * dy - Y * dx, rho2 + rd) * g.inv_dph;
+    const float e = 2.0f * rd + dd;
+    const float rhoq = sqrt_r(fmaxf(rho2 + e, 0.0f));
+    const float dsum = rhoq + rho;
+    const float drho = dsum > 0.0f ? e * rcpf(dsum) : 0.0f;
+    d1 = atan2_inc(Z * drho - rho * dz, Z * (Z + dz) + rho * rhoq) * g.inv_dth;
+  } else {
+    d0 = dx * g.inv_sp[0];
+    d1 = dy * g.inv_sp[1];
+    d2 = dz * g.inv_sp[2];
+  }
+  advance_cell(R.i0, R.fr0, d0);
+  advance_cell(R.i1, R.fr1, d1);
+  advance_cell(R.i2, R.fr2, d2);
+  if constexpr (KIND == RT_GRID_SPHERICAL_LOGR) {
+    if (R.i2 >= g.n2) R.i2 -= g.n2;
+    else if (R.i2 < 0) R.i2 += g.n2;
+  }
+}
+
 // Launch (Sec. 3.2): pixel centre (pu, pv) on the image plane; the ray starts on
 // the r_max sphere and travels along -o.
 __device__ __forceinline__ void pixel_start(const TraceArgs& a, int i, int j, double& pu, double& pv, double& b2,
@@ -562,17 +638,24 @@ __device__ __forceinline__ void pixel_start(const TraceArgs& a, int i, int j, do
 // Start ray `pix` (flat pixel index) of image `img` (= model * n_freq + freq):
 // r0 and its grid index come from the per-pixel table, p0 = n(r0) (-o).
 // Returns false for a ray that misses the model (its output is written).
-__device__ __forceinline__ bool init_ray(const TraceArgs& a, int img, int pix, RayState& R, CellCache& C) {
+template <class S, class Real>
+__device__ __forceinline__ bool init_ray(const TraceArgs& a, int img, int pix, RayStateT<S, Real>& R, CellCache& C) {
   const int npx = a.nu * a.nv;
   const int model = img / a.n_freq;
   const int fi = img - model * a.n_freq;
   const int id = img * npx + pix;
   const double* L = a.launch + size_t(pix) * 6;
-  R.rx = L[0]; R.ry = L[1]; R.rz = L[2];
-  R.b0 = L[3]; R.b1 = L[4]; R.b2 = L[5];
-  if (R.b0 < 0.0) {  // missing pixel: (rx, ry, rz) is its image-plane point, b1 its impact parameter
-    write_miss(a, id, R.b1, R.rx, R.ry, R.rz);
+  if (L[3] < 0.0) {  // missing pixel: L[0..2] is its image-plane point, L[4] its impact parameter
+    write_miss(a, id, L[4], L[0], L[1], L[2]);
     return false;
+  }
+  R.rx = S(L[0]); R.ry = S(L[1]); R.rz = S(L[2]);
+  if constexpr (std::is_same<S, double>::value) {
+    R.b0 = L[3]; R.b1 = L[4]; R.b2 = L[5];
+  } else {
+    split_index(L[3], R.i0, R.fr0);
+    split_index(L[4], R.i1, R.fr1);
+    split_index(L[5], R.i2, R.fr2);
   }
   C.key = -1;  // the lane's cached cell may belong to another model
   const double xf = a.xf[fi];
@@ -589,8 +672,8 @@ __device__ __forceinline__ bool init_ray(const TraceArgs& a, int img, int pix, R
     const float n2 = 1.0f - R.xff * a.launch_ne[size_t(model) * npx + pix];
     nidx = n2 > 0.f ? double(sqrt_fast(n2)) : 0.0;
   }
-  R.px = -nidx * a.o[0]; R.py = -nidx * a.o[1]; R.pz = -nidx * a.o[2];
-  R.A = 0.0; R.lam_tot = 0.0; R.tau = 0.0; R.lns = 0.0; R.s_arc = 0.0;
+  R.px = S(-nidx * a.o[0]); R.py = S(-nidx * a.o[1]); R.pz = S(-nidx * a.o[2]);
+  R.A = Real(0); R.lam_tot = Real(0); R.tau = Real(0); R.lns = Real(0); R.s_arc = S(0);
   R.rmin = float(a.g.r_max);
   R.lam_end = 1.0f;
   R.n = 0;
@@ -635,10 +718,11 @@ __device__ __forceinline__ void init_tube(const TraceArgs& a, RayState& R, CellC
   R.tube_ln_s = log(eps * eps);
 }
 
-__device__ __forceinline__ void finish_ray(const TraceArgs& a, const RayState& R) {
+template <class S, class Real>
+__device__ __forceinline__ void finish_ray(const TraceArgs& a, const RayStateT<S, Real>& R) {
   const double tbc = (R.code == kHit) ? a.tb_inner : a.tb_sky;
   const float trans = __builtin_amdgcn_exp2f(-1.44269504089f * float(R.lam_tot));
-  a.tb[R.id] = float(R.A + double(trans) * tbc);
+  a.tb[R.id] = float(double(R.A) + double(trans) * tbc);
   if (a.info) {
     rt_ray_info inf;
     inf.n_steps = R.n;
@@ -677,21 +761,25 @@ enum : int { kModeFlags = 0, kModeLos = 1, kModeNoMag = 2, kModeFull = 3, kModeC
 // termination R holds the end point, the code and the last-step fraction.
 // TAPE: when tp is not null, also write the step's record (fields kTape*,
 // field f at tp[f * ts]).
-template <bool MIXED, int KIND, int MODE = kModeFlags, bool TAPE = false>
-__device__ __forceinline__ int ray_step(const TraceArgs& a, RayState& R, CellCache& C, float* tp = nullptr,
-                                         size_t ts = 0) {
+// S, the precision of the state and of the step increments, comes from the ray
+// state's type; Real, that of the ray-tube area and the transfer, from MIXED.
+template <bool MIXED, int KIND, int MODE = kModeFlags, bool TAPE = false, class S>
+__device__ __forceinline__ int ray_step(const TraceArgs& a, RayStateT<S, typename RealOf<MIXED>::T>& R, CellCache& C,
+                                         float* tp = nullptr, size_t ts = 0) {
   using Real = typename RealOf<MIXED>::T;
+  constexpr bool s64 = std::is_same<S, double>::value;
   const bool refr = (MODE == kModeFlags) ? (a.flags & RT_USE_REFRACTION) != 0 : (MODE != kModeLos);
   const bool mag = (MODE == kModeFlags) ? refr && (a.flags & RT_USE_MAGNIFICATION) != 0 : (MODE == kModeFull);
   constexpr bool carried = MODE == kModeCarried;
+  static_assert(s64 || (!carried && !TAPE), "carried tubes and the adjoint record use FP64 state");
 
   // All evaluation points of this step are r_i + (FP32 offset).
   StepOrigin O;
   make_origin<KIND>(R, O);
   const float pxf = float(R.px), pyf = float(R.py), pzf = float(R.pz);
   float h;
-  double hd;
-  double drx, dry, drz, dpx = 0.0, dpy = 0.0, dpz = 0.0;
+  S hd;
+  S drx, dry, drz, dpx = S(0), dpy = S(0), dpz = S(0);
   float d2x = 0.f, d2y = 0.f, d2z = 0.f, d3x = 0.f, d3y = 0.f, d3z = 0.f;
   float F1x = 0.f, F1y = 0.f, F1z = 0.f, F2x = 0.f, F2y = 0.f, F2z = 0.f, F3x = 0.f, F3y = 0.f, F3z = 0.f;
   float sx = 0.f, sy = 0.f, sz = 0.f;                 // g1 + g2 + g3
@@ -709,7 +797,8 @@ __device__ __forceinline__ int ray_step(const TraceArgs& a, RayState& R, CellCac
       tp[kTapeNi * ts] = ni;
       tp[kTapeF1 * ts] = F1x; tp[(kTapeF1 + 1) * ts] = F1y; tp[(kTapeF1 + 2) * ts] = F1z;
     }
-    hd = (ni > a.n_floor) ? a.ds_max_d * rcp64(double(ni)) : a.ds_max_d * rcp64(a.n_floor_d);
+    if constexpr (s64) hd = (ni > a.n_floor) ? a.ds_max_d * rcp64(double(ni)) : a.ds_max_d * rcp64(a.n_floor_d);
+    else hd = a.ds_max * rcpf(fmaxf(ni, a.n_floor));
     h = float(hd);
     const float hh = 0.5f * h;
     d2x = hh * pxf; d2y = hh * pyf; d2z = hh * pzf;
@@ -731,18 +820,18 @@ __device__ __forceinline__ int ray_step(const TraceArgs& a, RayState& R, CellCac
       tp[kTapeT * ts] = tx; tp[(kTapeT + 1) * ts] = ty; tp[(kTapeT + 2) * ts] = tz;
     }
     // RK4: dr = h p + h^2/6 (F1 + F2 + F3), dp = h/6 (F1 + 2 F2 + 2 F3 + F4),
-    // F = -1/2 Xf grad n_e, the coefficient applied in FP64.
-    const double c6 = R.cfd * hd * (1.0 / 6.0);
-    drx = hd * R.px + hd * c6 * double(sx);
-    dry = hd * R.py + hd * c6 * double(sy);
-    drz = hd * R.pz + hd * c6 * double(sz);
-    dpx = c6 * double(tx);
-    dpy = c6 * double(ty);
-    dpz = c6 * double(tz);
+    // F = -1/2 Xf grad n_e, the coefficient applied in the state's precision.
+    const S c6 = (s64 ? S(R.cfd) : S(R.cf)) * hd * S(1.0 / 6.0);
+    drx = hd * R.px + hd * c6 * S(sx);
+    dry = hd * R.py + hd * c6 * S(sy);
+    drz = hd * R.pz + hd * c6 * S(sz);
+    dpx = c6 * S(tx);
+    dpy = c6 * S(ty);
+    dpz = c6 * S(tz);
   } else {
     // Straight line of sight: no force, |p| = 1, dt = ds_max.
     h = a.ds_max;
-    hd = a.ds_max_d;
+    hd = s64 ? S(a.ds_max_d) : S(a.ds_max);
     drx = hd * R.px; dry = hd * R.py; drz = hd * R.pz;
   }
   if constexpr (carried) {
@@ -850,16 +939,16 @@ __device__ __forceinline__ int ray_step(const TraceArgs& a, RayState& R, CellCac
   }
 
   // Termination on the two spheres, last chord truncated at the crossing.
-  const double nx = R.rx + drx, ny = R.ry + dry, nz = R.rz + drz;
-  const double r1sq = nx * nx + ny * ny + nz * nz;
+  const S nx = R.rx + drx, ny = R.ry + dry, nz = R.rz + drz;
+  const S r1sq = nx * nx + ny * ny + nz * nz;
   int code = kRunning;
-  double lam = 1.0;
-  if (a.g.has_inner && r1sq <= a.g.r_in * a.g.r_in) {
+  S lam = S(1);
+  if (a.g.has_inner && r1sq <= S(a.g.r_in * a.g.r_in)) {
     code = kHit;
-    lam = crossing<double>(R.rx, R.ry, R.rz, drx, dry, drz, a.g.r_in, false);
-  } else if (r1sq >= a.g.r_max * a.g.r_max && R.n >= 2) {
+    lam = crossing<S>(R.rx, R.ry, R.rz, drx, dry, drz, a.g.r_in, false);
+  } else if (r1sq >= S(a.g.r_max * a.g.r_max) && R.n >= 2) {
     code = kExit;
-    lam = crossing<double>(R.rx, R.ry, R.rz, drx, dry, drz, a.g.r_max, true);
+    lam = crossing<S>(R.rx, R.ry, R.rz, drx, dry, drz, a.g.r_max, true);
   } else if (R.n == a.max_steps) {
     code = kMaxSteps;
   }
@@ -875,20 +964,20 @@ __device__ __forceinline__ int ray_step(const TraceArgs& a, RayState& R, CellCac
     const float lt = __builtin_amdgcn_logf(te_m) * 0.69314718056f;
     const float lnl = (te_m >= 2.0e5f) ? 24.5f + lt - R.lnf : 18.2f + 1.5f * lt - R.lnf;
     const float kn = kFFCoefF * ne_m * ne_m * lnl * rcpf(R.f2 * te_m * sqrt_fast(te_m));
-    dtau = Real(kn) * Real(kRsunCm * lam * hd);
+    dtau = Real(kn) * (Real(kRsunCm) * Real(lam) * Real(hd));
   }
   const Real gamma = -Real(lam) * Real(lnM);
   const Real xs = dtau + gamma;
   // front to back: A += e^{-Lambda} T dtau phi(x), Lambda += x; the transmittance
   // is formed from the accumulated Lambda each step, so its error does not compound
   const float trans = __builtin_amdgcn_exp2f(-1.44269504089f * float(R.lam_tot));
-  R.A = double(Real(R.A) + Real(trans) * (Real(te_m) * dtau * Real(segment_phi(float(xs)))));
-  R.lam_tot = double(Real(R.lam_tot) + xs);
-  R.tau = double(Real(R.tau) + dtau);
-  R.lns = double(Real(R.lns) + Real(lam) * Real(lnM));
+  R.A = R.A + Real(trans) * (Real(te_m) * dtau * Real(segment_phi(float(xs))));
+  R.lam_tot = R.lam_tot + xs;
+  R.tau = R.tau + dtau;
+  R.lns = R.lns + Real(lam) * Real(lnM);
 
   if (R.path_slot >= 0) {
-    R.s_arc += lam * double(ds);
+    R.s_arc += lam * S(ds);
     if (R.path_len < a.path_cap) {
       float* rec = a.path_out + (size_t(R.path_slot) * a.path_cap + R.path_len) * kPathStride;
       rec[0] = float(R.rx + lam * drx); rec[1] = float(R.ry + lam * dry); rec[2] = float(R.rz + lam * drz);

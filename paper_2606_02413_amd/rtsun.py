@@ -23,6 +23,7 @@ RT_PREC_ALL_FP32 = 1 << 2
 RT_SCHED_PLAIN = 1 << 3
 RT_DETERMINISTIC_GRAD = 1 << 4
 RT_CARRIED_TUBE = 1 << 5
+RT_PREC_FP32_STEP = 1 << 6
 RT_TEST_NO_ABSORPTION = 1 << 30
 
 EXIT_OUTER, HIT_INNER, MISS, MAX_STEPS, NONFINITE = 1, 2, 3, 4, 5
@@ -164,13 +165,14 @@ def image_desc(n, half_width, obs_dir=(1.0, 0.0, 0.0), up=(0.0, 0.0, 1.0), nv=No
 
 def params(*, ds_max=0.005, n_floor=1.0, max_steps=200000, eta=1e-2, tb_inner=1.0e4, tb_sky=0.0,
            refraction=True, magnification=True, all_fp32=False, plain=False, no_absorption=False,
-           checkpoint_every=64, carried_tube=False):
+           checkpoint_every=64, carried_tube=False, fp32_step=False):
     p = Params()
     lib().rt_params_default(C.byref(p))
     f = 0
     f |= RT_USE_REFRACTION if refraction else 0
     f |= RT_USE_MAGNIFICATION if magnification else 0
     f |= RT_PREC_ALL_FP32 if all_fp32 else 0
+    f |= RT_PREC_FP32_STEP if fp32_step else 0
     f |= RT_SCHED_PLAIN if plain else 0
     f |= RT_TEST_NO_ABSORPTION if no_absorption else 0
     f |= RT_CARRIED_TUBE if carried_tube else 0
@@ -413,21 +415,39 @@ def gather_replay(model, freqs, image, prm, *, max_bytes=40 << 30, stream=None):
             "ray_steps_per_s": steps / (ms.value * 1e-3)}
 
 
+class CapturedTrace:
+    """A captured rt_trace_maps call: `replay()` re-runs the whole call (counter
+    and statistics fills, the launch table and the trace kernels) into the
+    tensors of `out`.  The graph was captured on `stream`, a stream of its own,
+    whose library tables it uses; the object keeps that stream alive."""
+
+    def __init__(self, graph, out, stream):
+        self.graph = graph
+        self.out = out
+        self.stream = stream
+
+    def replay(self):
+        self.graph.replay()
+
+
 def capture_trace_maps(models, freqs, image, prm, *, info=False, stats=True):
     """Capture one rt_trace_maps call (no path output) in a HIP graph.
 
-    Returns (graph, out): `graph.replay()` re-runs the whole call (counter and
-    statistics fills, the launch table and the trace kernels) into the tensors
-    of `out`.  A warm-up call first sizes the library's per-call tables, so the
-    captured call allocates nothing and only launches kernels on the capture
-    stream (every clear is a fill kernel, no memset node)."""
+    Returns (captured, out) with `captured.replay()` and the output tensors.  A
+    warm-up call on the capture stream first sizes that stream's library tables,
+    so the captured call allocates nothing and only launches kernels (every
+    clear is a fill kernel, no memset node)."""
     import torch
-    out = trace_maps(models, freqs, image, prm, info=info, stats=stats)
-    torch.cuda.synchronize()
+    stream = torch.cuda.Stream()
+    stream.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(stream):
+        out = trace_maps(models, freqs, image, prm, info=info, stats=stats)
+    stream.synchronize()
     graph = torch.cuda.CUDAGraph()
-    with torch.cuda.graph(graph):
+    with torch.cuda.graph(graph, stream=stream):
         trace_maps(models, freqs, image, prm, info=info, stats=stats, out=out)
-    return graph, out
+    torch.cuda.current_stream().wait_stream(stream)
+    return CapturedTrace(graph, out, stream), out
 
 
 def trace_adjoint(model, freqs, image, prm, weights, *, tb=True, stream=None, out=None):

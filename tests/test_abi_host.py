@@ -76,6 +76,22 @@ def test_model_load_validation(R):
     assert _load(R, good, ne, zt)[0] == 2
 
 
+
+def test_grid_capacity_limits(R):
+    """Cell keys are formed with 24-bit multiplies and kept in 32-bit ints: grids
+    with n0*n1 >= 2^24, a packed row of 2^24 or more, or more than 2^31-1 packed
+    vertices are refused before any value is read (the small arrays passed here
+    are never touched)."""
+    ne = np.full(8, 1e7, np.float32)
+    te = np.full(8, 1e6, np.float32)
+    for kind, shape in ((R.RT_GRID_SPHERICAL_LOGR, (4096, 4096, 3)),      # n0*n1 = 2^24
+                        (R.RT_GRID_CARTESIAN, (2, 2, 1 << 24)),            # row of 2^24
+                        (R.RT_GRID_SPHERICAL_LOGR, (2, 2, (1 << 24) - 1)),  # packed row n2 + 1 = 2^24
+                        (R.RT_GRID_SPHERICAL_LOGR, (2048, 2048, 512)),      # 2048*2048*513 > 2^31-1
+                        (R.RT_GRID_CARTESIAN, (2048, 2048, 512))):          # 2^31 > 2^31-1
+        st, msg = _load(R, R.grid_desc(kind, shape, 1.0, 3.0), ne, te)
+        assert st == 6, (shape, st, msg)
+
 def test_device_byte_cap(R, monkeypatch):
     monkeypatch.setenv("RT_MAX_DEVICE_BYTES", "100")
     good = R.grid_desc(R.RT_GRID_SPHERICAL_LOGR, (4, 3, 5), 1.0, 3.0)

@@ -11,7 +11,8 @@ magnification (Eqs. 5-12), transfer with the geometric term (Eqs. 2-3),
 two-stage transfer (Sec. 3.2).  Free-free constants: Dulk (1985).
 
 Parity unpinned (no closed form exists): the oracle on the random-field
-coronae beyond the invariants below; the oracle's grazing flags.
+coronae beyond the invariants below.  The ray flags are pinned in
+test_oracle_flags.py.
 """
 import math
 
@@ -240,6 +241,39 @@ def test_straight_line_limit_high_frequency(orc):
         d.append(abs(ref["tau"] / los["tau"] - 1))
     assert d[0] < 3e-3
     assert 6.0 < d[0] / d[1] < 12.0, d
+
+
+@pytest.mark.parametrize("tbc", [0.0, 3.0e5])
+def test_transfer_closed_form_with_absorption_and_tube_term(orc, tbc):
+    """Both terms of the transfer step at once (Eqs. 2-3, 12): n_e = n0 + a0 (x^2 + y^2)
+    (a uniform background with a quadratic lens about the z axis), isothermal, and
+    the central ray down the axis.  On the axis kappa is constant; with n_floor = 1
+    every step has the same dt; the perturbed rays are transverse oscillators
+    x'' = -beta x (beta = Xf a0), so every full step has the same
+    M = (1 - beta dt^2/2 + beta^2 dt^4/24)^2.  Per unit ray parameter t the optical
+    depth grows at k = kappa n R_sun and the tube term at g = -ln M / dt, both
+    constant, so the transfer is dT/dt = k T_e - (k + g) T with the solution
+      T_b = T_e k/(k + g) (1 - e^{-(k+g) L}) + T_bc e^{-(k+g) L},  L = 2 r_max / n
+    (the t-length of the chord).  A step update that drops gamma from either
+    factor, or takes it with the wrong sign, misses this by ~1e-3 or more."""
+    f, T, rmax, h, beta = 100e6, 1.0e6, 1.0, 0.01, 100.0
+    xf = xf_of(f)
+    n0 = math.sqrt(1.0 / (R_SUN_CM * kappa_dulk(1.0, T, f)))  # k = 1 per unit t
+    med = orc.OracleMedium(orc.ANALYTIC_LENS, r_in=-1.0, r_max=rmax, a0=beta / xf, a1=n0, t_const=T)
+    P = orc.make_params(ds_max=h, n_floor=1.0, tb_sky=tbc, tb_inner=tbc)
+    res = orc.trace_launch(med, P, f, [0.0, 0.0, rmax], [0.0, 0.0, -1.0])[0]
+    n = math.sqrt(1.0 - xf * n0)
+    k = kappa_dulk(n0, T, f) * R_SUN_CM
+    lnM = 2.0 * math.log(1.0 - beta * h * h / 2.0 + beta ** 2 * h ** 4 / 24.0)
+    g = -lnM / h
+    L = 2.0 * rmax / n
+    want = T * k / (k + g) * (-math.expm1(-(k + g) * L)) + tbc * math.exp(-(k + g) * L)
+    assert res["code"] == orc.EXIT_OUTER
+    assert abs(res["tau"] / (k * L) - 1) < 1e-12
+    assert abs(res["ln_s_end"] / (lnM * L / h) - 1) < 1e-11
+    # both terms matter here: optical depth ~2.3 and tube term ~2.3 over the ray
+    assert k * L > 1.0 and g * L > 1.0
+    assert abs(res["tb"] / want - 1) < 1e-11, (res["tb"], want)
 
 
 def test_back_to_front_equals_front_to_back(orc):
