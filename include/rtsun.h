@@ -253,6 +253,25 @@ rt_status rt_trace_maps(const rt_model* const* models, int32_t n_models, const d
                         const int32_t* path_rays, int32_t n_path_rays, int32_t path_capacity,
                         float* path_out, int32_t* path_len_out, void* hip_stream);
 
+/* rt_trace_maps without any device allocation, for callers that cannot
+ * allocate: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  Same arguments and results as rt_trace_maps (bitwise
+ * equal), without path outputs.  The per-call tables (claim counters, the
+ * per-pixel launch table, n_e at the start points) live in a fixed device array
+ * of RT_STATIC_SCRATCH_BYTES per device, held from the library's first use on
+ * that device until the process ends; a call needs
+ * 256 + ceil256(48 nu nv) + 4 nu nv n_models bytes of it (RT_E_CAPACITY beyond:
+ * a 1024 x 1024 image with up to 3 models fits).  Every call of this entry
+ * point on a device shares that array and leaves its contents behind: calls
+ * that overlap in time on one device (different streams, or a replayed graph
+ * beside another call) race; issue them on one stream.  Errors as
+ * rt_trace_maps. */
+#define RT_STATIC_SCRATCH_BYTES (64u << 20)
+rt_status rt_trace_maps_static(const rt_model* const* models, int32_t n_models, const double* freq_hz,
+                               int32_t n_freq, const rt_image_desc* image, const rt_params* params,
+                               float* tb_out, rt_ray_info* info_out, rt_trace_stats* stats_out,
+                               void* hip_stream);
+
 /* Reverse-mode gradient of L = sum_{f,i,j} w[f][i][j] T_b[f][i][j] with
  * respect to ln n_e and ln T at every grid vertex, for one model: the exact
  * derivative of the discrete forward of rt_trace_maps (Sec. 2.1 Eq. 4 ray

@@ -99,6 +99,15 @@ constexpr long long kAdjCheckpointBudget = 8ll << 30;  // bytes of per-ray check
 std::mutex g_scratch_mu;
 DeviceScratch g_scratch[64];
 
+// Fixed device scratch of rt_trace_maps_static: one array per device, held from
+// the library's load on that device until the process ends.  Host code never
+// uses the array's name as an address: the device address comes from
+// hipGetSymbolAddress, once per device (g_static_ptr).
+constexpr size_t kStaticScratchBytes = size_t(RT_STATIC_SCRATCH_BYTES);
+constexpr size_t kStaticCountersBytes = 256;  // kXcds claim counters, padded
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+void* g_static_ptr[64] = {};
+
 
 // Call with g_scratch_mu held.
 rt_status scratch_for(int dev, DeviceScratch** out) {
@@ -599,6 +608,60 @@ rt_status rt_trace_maps(const rt_model* const* models, int32_t n_models, const d
       tune = sc->tune;
     }
     return enqueue_trace(a, *params, sc->n_cu, tune, tb->counters, s);
+  } catch (...) {
+    return fail(RT_E_INTERNAL, "unexpected exception");
+  }
+}
+
+rt_status rt_trace_maps_static(const rt_model* const* models, int32_t n_models, const double* freq_hz,
+                               int32_t n_freq, const rt_image_desc* image, const rt_params* params, float* tb_out,
+                               rt_ray_info* info_out, rt_trace_stats* stats_out, void* hip_stream) {
+  try {
+    if (!tb_out) return fail(RT_E_INVALID_ARG, "tb_out is NULL");
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    TraceArgs a{};
+    rt_status st = validate_call(models, n_models, freq_hz, n_freq, image, params, a);
+    if (st != RT_OK) return st;
+    const size_t lt = (launch_table_bytes(a) + 255) / 256 * 256;
+    const size_t ne = start_ne_bytes(a);
+    if (kStaticCountersBytes + lt + ne > kStaticScratchBytes)
+      return fail(RT_E_CAPACITY, "rt_trace_maps_static: the call needs " +
+                                     std::to_string(kStaticCountersBytes + lt + ne) + " bytes of scratch, more than " +
+                                     std::to_string(kStaticScratchBytes) + " (nu*nv*(48 + 4*n_models) + 256)");
+    const int dev = models[0]->device;
+    st = hip_check(hipSetDevice(dev), "hipSetDevice");
+    if (st != RT_OK) return st;
+    DeviceScratch* sc = nullptr;
+    rt_tuning tune;
+    char* base = nullptr;
+    {
+      std::lock_guard<std::mutex> lk(g_scratch_mu);
+      st = scratch_for(dev, &sc);
+      if (st != RT_OK) return st;
+      if (!g_static_ptr[dev]) {
+        void* ptr = nullptr;
+        st = hip_check(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+        if (st != RT_OK) return st;
+        g_static_ptr[dev] = ptr;
+      }
+      base = static_cast<char*>(g_static_ptr[dev]);
+      tune = sc->tune;
+    }
+    unsigned* counters = reinterpret_cast<unsigned*>(base);
+    double* launch = reinterpret_cast<double*>(base + kStaticCountersBytes);
+    float* start_ne = reinterpret_cast<float*>(base + kStaticCountersBytes + lt);
+    a.launch = launch;
+    a.launch_ne = start_ne;
+    st = hip_check(launch_start_index(a, launch, start_ne, s), "start index");
+    if (st != RT_OK) return st;
+    a.tb = tb_out;
+    a.info = info_out;
+    a.stats = stats_out;
+    if (stats_out) {
+      st = hip_check(launch_fill_u32(reinterpret_cast<unsigned*>(stats_out), 0u, sizeof(rt_trace_stats) / 4, s), "stats fill");
+      if (st != RT_OK) return st;
+    }
+    return enqueue_trace(a, *params, sc->n_cu, tune, counters, s);
   } catch (...) {
     return fail(RT_E_INTERNAL, "unexpected exception");
   }

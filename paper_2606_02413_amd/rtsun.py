@@ -92,6 +92,9 @@ def lib():
                                     C.POINTER(ImageDesc), C.POINTER(Params), vp, vp, vp, C.POINTER(C.c_int32),
                                     C.c_int32, C.c_int32, vp, vp, vp]
         L.rt_trace_maps.restype = C.c_int
+        L.rt_trace_maps_static.argtypes = [C.POINTER(vp), C.c_int32, C.POINTER(C.c_double), C.c_int32,
+                                           C.POINTER(ImageDesc), C.POINTER(Params), vp, vp, vp, vp]
+        L.rt_trace_maps_static.restype = C.c_int
         L.rt_trace_adjoint.argtypes = [vp, C.POINTER(C.c_double), C.c_int32, C.POINTER(ImageDesc),
                                        C.POINTER(Params), vp, vp, vp, vp, vp, vp]
         L.rt_trace_adjoint.restype = C.c_int
@@ -413,6 +416,32 @@ def gather_replay(model, freqs, image, prm, *, max_bytes=40 << 30, stream=None):
                                         _stream_ptr(stream)))
     return {"walks": n_rays, "capacity": cap, "ray_steps": steps, "ms": ms.value,
             "ray_steps_per_s": steps / (ms.value * 1e-3)}
+
+
+def trace_maps_static(models, freqs, image, prm, *, info=True, stats=True, stream=None, out=None):
+    """rt_trace_maps_static: trace_maps without any device allocation by the
+    library (per-call tables in its fixed device array; no path outputs).  The
+    output tensors are allocated here unless passed in `out`."""
+    import torch
+    if isinstance(models, Model):
+        models = [models]
+    freqs = np.ascontiguousarray(np.atleast_1d(freqs), dtype=np.float64)
+    M, F = len(models), freqs.shape[0]
+    dev = torch.device("cuda", models[0].device)
+    shape = (M, F, image.nv, image.nu)
+    res = {} if out is None else out
+    if "tb" not in res:
+        res["tb"] = torch.empty(shape, dtype=torch.float32, device=dev)
+    if info and "info" not in res:
+        res["info"] = torch.empty(shape + (32,), dtype=torch.uint8, device=dev)
+    if stats and "stats" not in res:
+        res["stats"] = torch.empty(40, dtype=torch.uint8, device=dev)
+    handles = (C.c_void_p * M)(*[m.handle.value for m in models])
+    ptr = lambda k: C.c_void_p(res[k].data_ptr()) if k in res and res[k] is not None else C.c_void_p(0)
+    _check(lib().rt_trace_maps_static(handles, M, freqs.ctypes.data_as(C.POINTER(C.c_double)), F, C.byref(image),
+                                      C.byref(prm), ptr("tb"), ptr("info") if info else C.c_void_p(0),
+                                      ptr("stats") if stats else C.c_void_p(0), _stream_ptr(stream)))
+    return res
 
 
 class CapturedTrace:
