@@ -683,15 +683,34 @@ def gradcheck_study(n_pixels=64, n_cells=200, h=1e-3):
                    "tape_vs_fd": abs(go - d1) / abs(d1) if d1 != 0 else float("inf"),
                    "steps_and_codes_unchanged": same1}
             if row["adjoint_vs_fd"] > 1e-4:
+                # is the difference the FD's own (kinks of the piecewise-trilinear
+                # discrete map within +-h)?  FD at smaller h, against the adjoint
                 d2, same2 = fd(0.5 * h)
                 row["fd_half_h"] = d2
                 row["fd_h_vs_half_h"] = abs(d1 - d2) / abs(d2) if d2 != 0 else float("inf")
                 row["adjoint_vs_fd_half_h"] = abs(gg - d2) / abs(d2) if d2 != 0 else float("inf")
+                for hs in (1e-4, 1e-5):
+                    ds_, _ = fd(hs)
+                    row[f"adjoint_vs_fd_{hs:g}"] = abs(gg - ds_) / abs(ds_) if ds_ != 0 else float("inf")
+                    row[f"tape_vs_fd_{hs:g}"] = abs(go - ds_) / abs(ds_) if ds_ != 0 else float("inf")
             rows.append(row)
+            if len(rows) % 10 == 0:
+                progress(f"gradcheck {name}: {len(rows)} of {len(cells)} cells, "
+                         f"{sum(r['adjoint_vs_fd'] <= 1e-4 for r in rows)} within 1e-4 at h")
         t_fd = time.perf_counter() - t2
         within = [r["adjoint_vs_fd"] <= 1e-4 for r in rows]
         outl = [r for r in rows if r["adjoint_vs_fd"] > 1e-4]
+        conv = {}
+        for hs in (1e-4, 1e-5):
+            v = [r[f"adjoint_vs_fd_{hs:g}"] for r in outl]
+            conv[f"outliers_within_1e-4_at_h_{hs:g}"] = int(sum(x <= 1e-4 for x in v))
+            conv[f"outliers_median_adjoint_vs_fd_at_h_{hs:g}"] = float(np.median(v)) if v else 0.0
         fields.append({"field": name, "cells": len(rows), "fraction_within_1e-4": float(np.mean(within)),
+                       "outlier_convergence": conv,
+                       # within 1e-4 at h, or else at one of the smaller h
+                       "fraction_within_1e-4_any_h": float(np.mean(
+                           [min(r["adjoint_vs_fd"], r.get("adjoint_vs_fd_0.0001", 1.0),
+                                r.get("adjoint_vs_fd_1e-05", 1.0)) <= 1e-4 for r in rows])),
                        "tape_fraction_within_1e-4": float(np.mean([r["tape_vs_fd"] <= 1e-4 for r in rows])),
                        "median_adjoint_vs_fd": float(np.median([r["adjoint_vs_fd"] for r in rows])),
                        "outliers": outl, "fd_seconds": round(t_fd, 1)})
@@ -706,13 +725,15 @@ def fit_params_study(iters):
     and 8 active-region density factors from its 8-frequency maps: the structured
     model's generator on a 128x64x128 grid (r 1-30, seed 5), 128^2 image over
     +/-1.5 R_sun, 8 frequencies 40-800 MHz; the fit starts from s = 0.25,
-    T_bg = 1.6 MK, A_k = 4.5."""
+    T_bg = 1.6 MK, A_k = 4.5: ITERS Adam steps (learning rate 0.02 x 0.95^step),
+    then 8 L-BFGS iterations."""
     from paper_2606_02413_amd import corona
     from paper_2606_02413_amd.fitting import fit_params
     kw = dict(nr=128, nt=64, nph=128, r_in=1.0, r_max=30.0, seed=5, n_ar=8, n_feat=512)
     start = np.concatenate([[0.25, math.log(1.6e6)], np.full(8, math.log(3.5))])
     t0 = time.perf_counter()
-    truth, hist, th = fit_params(kw, 128, 1.5, corona.log_freqs(8), iters, 0.03, start, log=progress)
+    truth, hist, th = fit_params(kw, 128, 1.5, corona.log_freqs(8), iters, 0.02, start, log=progress, decay=0.95,
+                                 polish=8)
     a_true = 1.0 + np.exp(truth[2:])
     a_fit = 1.0 + np.exp(th[2:])
     print(json.dumps({"study": "fit-params", "model": "128x64x128 structured (r 1-30, seed 5, 8 active regions)",

@@ -104,8 +104,11 @@ rt_status rt_model_load(const rt_grid_desc* desc, const float* ne, const float* 
 
 /* Replace a model's values (same shape).  on_device = 0: host pointers,
  * validated on the host; on_device = 1: device pointers on the model's device,
- * validated by a device reduction (this synchronises `hip_stream`).  Must not
- * race a trace that reads the same model. */
+ * validated by a device reduction (this synchronises `hip_stream`);
+ * on_device = 2: device pointers to the natural logarithms ln n_e, ln T (the
+ * variables of the differentiable forward), exponentiated on the device and
+ * then validated like on_device = 1.  Must not race a trace that reads the same
+ * model. */
 rt_status rt_model_update(rt_model* model, const float* ne, const float* te, int32_t on_device,
                           void* hip_stream);
 
@@ -308,6 +311,14 @@ rt_status rt_trace_adjoint(const rt_model* model, const double* freq_hz, int32_t
                            const rt_image_desc* image, const rt_params* params, const float* weights,
                            double* loss_out, float* grad_ln_ne, float* grad_ln_te, float* tb_out,
                            void* hip_stream);
+
+/* Beam FWHM in R_sun of an interferometer with maximum baseline `baseline_m`
+ * (metres) at each frequency: lambda / B radians over the angle 1 R_sun
+ * subtends at 1 au (the beam scale of the paper's convolved maps, Sec. 3.3;
+ * the form lambda / B is this library's reading).  freq_hz, fwhm_out: HOST
+ * [n].  Errors: RT_E_INVALID_ARG for NULL pointers, n < 1, a baseline or a
+ * frequency that is not finite and > 0. */
+rt_status rt_beam_fwhm(const double* freq_hz, int32_t n, double baseline_m, double* fwhm_out);
 
 /* Maps convolved with a Gaussian beam (the interferometric beam the paper
  * applies to its synthetic maps, Sec. 3.3).  maps_in, maps_out: DEVICE float32

@@ -444,6 +444,18 @@ const char* rt_status_string(rt_status s) {
 
 const char* rt_last_error_message(void) { return g_err.c_str(); }
 
+rt_status rt_beam_fwhm(const double* freq_hz, int32_t n, double baseline_m, double* fwhm_out) {
+  if (!freq_hz || !fwhm_out || n < 1) return fail(RT_E_INVALID_ARG, "freq_hz and fwhm_out need n >= 1 entries");
+  if (!(std::isfinite(baseline_m) && baseline_m > 0.0)) return fail(RT_E_INVALID_ARG, "baseline_m must be > 0");
+  const double c = 299792458.0;                     // speed of light [m/s]
+  const double r_sun_over_au = 6.957e8 / 1.495978707e11;  // angle 1 R_sun subtends at 1 au [rad]
+  for (int k = 0; k < n; ++k) {
+    if (!(std::isfinite(freq_hz[k]) && freq_hz[k] > 0.0)) return fail(RT_E_INVALID_ARG, "frequencies must be > 0");
+    fwhm_out[k] = (c / freq_hz[k] / baseline_m) / r_sun_over_au;
+  }
+  return RT_OK;
+}
+
 void rt_params_default(rt_params* p) {
   if (!p) return;
   std::memset(p, 0, sizeof(*p));
@@ -517,7 +529,7 @@ rt_status rt_model_update(rt_model* m, const float* ne, const float* te, int32_t
   try {
     if (!m) return fail(RT_E_INVALID_ARG, "model is NULL");
     if (!ne || !te) return fail(RT_E_INVALID_ARG, "ne/te is NULL");
-    if (on_device != 0 && on_device != 1) return fail(RT_E_INVALID_ARG, "on_device must be 0 or 1");
+    if (on_device < 0 || on_device > 2) return fail(RT_E_INVALID_ARG, "on_device must be 0, 1 or 2");
     const long long n = (long long)m->desc.n0 * m->desc.n1 * m->desc.n2;
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
     rt_status st = hip_check(hipSetDevice(m->device), "hipSetDevice");
@@ -529,7 +541,14 @@ rt_status rt_model_update(rt_model* m, const float* ne, const float* te, int32_t
       if (st == RT_OK) st = hip_check(hipMemcpyAsync(m->raw_te, te, m->raw_bytes, hipMemcpyHostToDevice, s), "copy T");
       if (st != RT_OK) return st;
     } else {
-      // Device inputs: count invalid values with a reduction, then copy.
+      // Device inputs (on_device 2: their logarithms, exponentiated into the
+      // staging copies first): count invalid values with a reduction, then copy.
+      if (on_device == 2) {
+        st = hip_check(launch_exp_pair(ne, te, n, m->raw_ne, m->raw_te, s), "exp kernel");
+        if (st != RT_OK) return st;
+        ne = m->raw_ne;
+        te = m->raw_te;
+      }
       int* bad = nullptr;
       st = dev_alloc((void**)&bad, sizeof(int), "validation counter");
       if (st != RT_OK) return st;
@@ -542,9 +561,11 @@ rt_status rt_model_update(rt_model* m, const float* ne, const float* te, int32_t
       if (st != RT_OK) return st;
       if (hbad != 0)
         return fail(RT_E_NONFINITE_INPUT, std::to_string(hbad) + " model values are not finite or out of range");
-      st = hip_check(hipMemcpyAsync(m->raw_ne, ne, m->raw_bytes, hipMemcpyDeviceToDevice, s), "copy n_e");
-      if (st == RT_OK) st = hip_check(hipMemcpyAsync(m->raw_te, te, m->raw_bytes, hipMemcpyDeviceToDevice, s), "copy T");
-      if (st != RT_OK) return st;
+      if (on_device == 1) {
+        st = hip_check(hipMemcpyAsync(m->raw_ne, ne, m->raw_bytes, hipMemcpyDeviceToDevice, s), "copy n_e");
+        if (st == RT_OK) st = hip_check(hipMemcpyAsync(m->raw_te, te, m->raw_bytes, hipMemcpyDeviceToDevice, s), "copy T");
+        if (st != RT_OK) return st;
+      }
     }
     return stage_model(m, s);
   } catch (...) {

@@ -110,6 +110,7 @@ hipError_t launch_disc_mean(const DiscArgs& d, const float* maps, double* out, h
 hipError_t launch_pack(const DevGeom& g, const float* ne, const float* te, float4* nfg, float* te_out,
                        hipStream_t s);
 hipError_t launch_validate(const float* ne, const float* te, long long n, int* bad, hipStream_t s);
+hipError_t launch_exp_pair(const float* lne, const float* lte, long long n, float* ne, float* te, hipStream_t s);
 hipError_t launch_fill_u32(unsigned* p, unsigned val, long long n, hipStream_t s);
 hipError_t launch_count_diff(const unsigned* a, const unsigned* b, long long n, unsigned* count, hipStream_t s);
 // prec: kPrecDefault, kPrecFp32Step or kPrecFp32 (rt_trace.hpp), from precision_of(flags)

@@ -58,6 +58,15 @@ __global__ void k_validate(const float* __restrict__ ne, const float* __restrict
   if (cnt) atomicAdd(bad, cnt);
 }
 
+// Model values from their natural logarithms: n_e = exp(ln n_e), T = exp(ln T).
+__global__ void k_exp_pair(const float* __restrict__ lne, const float* __restrict__ lte, long long n,
+                           float* __restrict__ ne, float* __restrict__ te) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    ne[i] = expf(lne[i]);
+    te[i] = expf(lte[i]);
+  }
+}
+
 __global__ void k_fill_u32(unsigned* p, unsigned v, long long n) {
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
     p[i] = v;
@@ -314,6 +323,11 @@ hipError_t launch_pack(const DevGeom& g, const float* ne, const float* te, float
 
 hipError_t launch_validate(const float* ne, const float* te, long long n, int* bad, hipStream_t s) {
   hipLaunchKernelGGL(k_validate, dim3(grid_for(n, 256)), dim3(256), 0, s, ne, te, n, bad);
+  return hipGetLastError();
+}
+
+hipError_t launch_exp_pair(const float* lne, const float* lte, long long n, float* ne, float* te, hipStream_t s) {
+  hipLaunchKernelGGL(k_exp_pair, dim3(grid_for(n, 256)), dim3(256), 0, s, lne, lte, n, ne, te);
   return hipGetLastError();
 }
 

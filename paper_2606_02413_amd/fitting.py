@@ -44,11 +44,13 @@ class ParamCorona:
         return ln_ne.reshape(shape).float(), ln_te.reshape(shape).float()
 
 
-def fit_params(cor_kw, n_pix, half, freqs, iters, lr, start, log=None, log_every=10):
-    """Adam on theta of ParamCorona against the maps of the truth (the same
-    parameterisation at its drawn values), through rtsun_function(): forward
-    rt_trace_maps, backward rt_trace_adjoint, chained to theta by torch.  Returns
-    the truth, the history and the final theta."""
+def fit_params(cor_kw, n_pix, half, freqs, iters, lr, start, log=None, log_every=10, decay=1.0, polish=0):
+    """Fit theta of ParamCorona to the maps of the truth (the same
+    parameterisation at its drawn values) through rtsun_function(): forward
+    rt_trace_maps, backward rt_trace_adjoint, chained to theta by torch.  Loss =
+    mean squared T_b difference / mean squared data.  `iters` Adam steps with
+    learning rate lr * decay^step, then `polish` L-BFGS iterations (strong Wolfe
+    line search).  Returns the truth, the history and the final theta."""
     import torch
     from . import corona, rtsun as R
     parts = corona.structured_parts(device="cuda", **cor_kw)
@@ -67,22 +69,43 @@ def fit_params(cor_kw, n_pix, half, freqs, iters, lr, start, log=None, log_every
         data = F.apply(ln_ne, ln_te, model, freqs, im, prm).clone()
     norm = float((data.double() ** 2).mean())
     theta = torch.tensor(start, dtype=torch.float64, device="cuda", requires_grad=True)
-    opt = torch.optim.Adam([theta], lr=lr)
     hist = []
-    for it in range(iters + 1):
-        opt.zero_grad()
+
+    def objective():
         ne_t, te_t = pc(theta, shape)
         tb = F.apply(ne_t, te_t, model, freqs, im, prm)
-        loss = ((tb.double() - data.double()) ** 2).mean() / norm
-        loss.backward()
+        return ((tb.double() - data.double()) ** 2).mean() / norm
+
+    def record(step, loss, kind):
         th = theta.detach().cpu().numpy()
-        hist.append({"step": it, "loss": float(loss), "s": float(th[0]), "T_bg": float(math.exp(th[1])),
-                     "A": (1.0 + np.exp(th[2:])).tolist()})
-        if log is not None and it % log_every == 0:
-            log(f"fit-params step {it}: loss {float(loss):.3e} s {th[0]:+.4f} T_bg {math.exp(th[1]):.4e}")
-        if it < iters:
-            opt.step()
+        hist.append({"step": step, "kind": kind, "loss": float(loss), "s": float(th[0]),
+                     "T_bg": float(math.exp(th[1])), "A": (1.0 + np.exp(th[2:])).tolist()})
+        if log is not None and (step % log_every == 0 or kind == "lbfgs"):
+            log(f"fit-params {kind} step {step}: loss {float(loss):.3e} s {th[0]:+.4f} T_bg {math.exp(th[1]):.4e}")
+
+    opt = torch.optim.Adam([theta], lr=lr)
+    sched = torch.optim.lr_scheduler.ExponentialLR(opt, gamma=decay)
+    for it in range(iters):
+        opt.zero_grad()
+        loss = objective()
+        loss.backward()
+        record(it, loss, "adam")
+        opt.step()
+        sched.step()
+    if polish > 0:
+        lb = torch.optim.LBFGS([theta], lr=1.0, max_iter=8, history_size=10, line_search_fn="strong_wolfe")
+
+        def closure():
+            lb.zero_grad()
+            loss = objective()
+            loss.backward()
+            return loss
+
+        for k in range(polish):
+            lb.step(closure)
+            with torch.no_grad():
+                record(iters + k, objective(), "lbfgs")
+    with torch.no_grad():
+        record(iters + polish, objective(), "final")
     model.close()
     return truth, hist, theta.detach().cpu().numpy()
-
-

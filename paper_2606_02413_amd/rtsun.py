@@ -116,6 +116,8 @@ def lib():
                                   C.POINTER(Params), C.c_int32, C.POINTER(Tuning), C.POINTER(C.c_double),
                                   C.POINTER(C.c_double), vp]
         L.rt_autotune.restype = C.c_int
+        L.rt_beam_fwhm.argtypes = [C.POINTER(C.c_double), C.c_int32, C.c_double, C.POINTER(C.c_double)]
+        L.rt_beam_fwhm.restype = C.c_int
         L.rt_beam_convolve.argtypes = [vp, vp, C.c_int32, C.c_int32, C.c_int32, C.c_double, C.c_double,
                                        C.POINTER(C.c_double), vp]
         L.rt_beam_convolve.restype = C.c_int
@@ -213,6 +215,13 @@ class Model:
         assert ne_t.is_contiguous() and te_t.is_contiguous()
         _check(lib().rt_model_update(self.handle, C.c_void_p(ne_t.data_ptr()), C.c_void_p(te_t.data_ptr()), 1,
                                      _stream_ptr(stream)))
+
+    def update_device_log(self, ln_ne_t, ln_te_t, stream=None):
+        """Replace values from the natural logarithms (float32 device tensors,
+        C-order, same shape); the library exponentiates them."""
+        assert ln_ne_t.is_contiguous() and ln_te_t.is_contiguous()
+        _check(lib().rt_model_update(self.handle, C.c_void_p(ln_ne_t.data_ptr()), C.c_void_p(ln_te_t.data_ptr()),
+                                     2, _stream_ptr(stream)))
 
     def update_host(self, ne, te, stream=None):
         ne = np.ascontiguousarray(ne, dtype=np.float32)
@@ -342,8 +351,11 @@ def autotune(models, freqs, image, prm, *, max_freqs=8, cache=None, stream=None)
 def beam_fwhm(freqs, baseline_m):
     """Beam FWHM in R_sun of an interferometer with maximum baseline `baseline_m`
     (metres): lambda / B radians, over the angle 1 R_sun subtends at 1 au."""
-    lam = 299792458.0 / np.asarray(freqs, dtype=np.float64)
-    return (lam / float(baseline_m)) / (6.957e8 / 1.495978707e11)
+    f = np.ascontiguousarray(np.atleast_1d(freqs), dtype=np.float64)
+    out = np.empty_like(f)
+    _check(lib().rt_beam_fwhm(f.ctypes.data_as(C.POINTER(C.c_double)), f.shape[0], float(baseline_m),
+                              out.ctypes.data_as(C.POINTER(C.c_double))))
+    return out
 
 
 def beam_convolve(maps, image, fwhm, *, stream=None, out=None):
@@ -515,24 +527,25 @@ def _make_function():
     class RTSunFunction(torch.autograd.Function):
         """T_b maps of one model as a differentiable function of (ln n_e, ln T).
 
-        forward: n_e = exp(ln n_e), T = exp(ln T) replace the model's values
-        (rt_model_update), then rt_trace_maps; backward: rt_trace_adjoint with the
-        incoming gradient of the maps as the loss weights."""
+        forward: the model's values are replaced from (ln n_e, ln T)
+        (rt_model_update, which exponentiates on the device), then rt_trace_maps;
+        backward: rt_trace_adjoint with the incoming gradient of the maps as the
+        loss weights."""
 
         @staticmethod
         def forward(ctx, ln_ne, ln_te, model, freqs, image, prm):
-            ne = torch.exp(ln_ne.detach()).to(torch.float32).contiguous()
-            te = torch.exp(ln_te.detach()).to(torch.float32).contiguous()
-            model.update_device(ne, te)
+            ln_ne_c = ln_ne.detach().to(torch.float32).contiguous()
+            ln_te_c = ln_te.detach().to(torch.float32).contiguous()
+            model.update_device_log(ln_ne_c, ln_te_c)
             out = trace_maps([model], freqs, image, prm, info=False, stats=False)
-            ctx.save_for_backward(ne, te)
+            ctx.save_for_backward(ln_ne_c, ln_te_c)
             ctx.model, ctx.freqs, ctx.image, ctx.prm = model, freqs, image, prm
             return out["tb"][0]
 
         @staticmethod
         def backward(ctx, grad_tb):
-            ne, te = ctx.saved_tensors
-            ctx.model.update_device(ne, te)  # the model may have been changed since the forward
+            ln_ne_c, ln_te_c = ctx.saved_tensors
+            ctx.model.update_device_log(ln_ne_c, ln_te_c)  # the model may have been changed since the forward
             w = grad_tb.detach().to(torch.float32).contiguous()
             res = trace_adjoint(ctx.model, ctx.freqs, ctx.image, ctx.prm, w, tb=False)
             return res["grad_ln_ne"], res["grad_ln_te"], None, None, None, None

@@ -151,6 +151,16 @@ def test_map_postprocessing_validation(R):
     assert L.rt_disc_mean(buf, 1, 8, 8, 1.0, 1.0, 0.0, other, None) == 1
     assert L.rt_disc_mean(buf, 1, 0, 8, 1.0, 1.0, 0.5, other, None) == 1
     assert abs(R.beam_fwhm([40e6], 15e3)[0] - 0.1074) < 1e-3   # 7.49 m / 15 km = 5.0e-4 rad
+    # lambda / B in units of the 1 au angle of 1 R_sun, at two frequencies
+    fw = R.beam_fwhm([100e6, 300e6], 5e3)
+    assert abs(fw[0] / (299792458.0 / 100e6 / 5e3 / (6.957e8 / 1.495978707e11)) - 1) < 1e-15
+    assert abs(fw[0] / fw[1] - 3.0) < 1e-14
+    L = R.lib()
+    out = (C.c_double * 1)()
+    f = (C.c_double * 1)(100e6)
+    assert L.rt_beam_fwhm(f, 1, 0.0, out) == 1
+    assert L.rt_beam_fwhm(f, 0, 5e3, out) == 1
+    assert L.rt_beam_fwhm((C.c_double * 1)(-1.0), 1, 5e3, out) == 1
 
 
 def test_read_probe_validation(R):
