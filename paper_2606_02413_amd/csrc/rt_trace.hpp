@@ -135,6 +135,10 @@ __device__ __forceinline__ double rcp64(double x) {
 // with the hardware estimate refined by two Newton steps (full FP64 accuracy,
 // not correctly rounded).  0 for x <= 0.
 __device__ __forceinline__ float sqrt_fast(float x) { return __builtin_amdgcn_sqrtf(x); }
+// Reciprocal square root with the hardware instruction: rsqrtf() adds a
+// rescaling for denormal arguments, which the radii and cylinder radii it is
+// used for never are (the same result otherwise).
+__device__ __forceinline__ float rsqrt_fast(float x) { return __builtin_amdgcn_rsqf(x); }
 __device__ __forceinline__ double rsqrt64(double x) {
   double y = __builtin_amdgcn_rsq(x);
   const double hx = 0.5 * x;
@@ -146,7 +150,7 @@ __device__ __forceinline__ double sqrt64(double x) { return x > 0.0 ? x * rsqrt6
 // The same for the precision of the ray-tube area (double, or float in the
 // all-FP32 variant).
 __device__ __forceinline__ double rsqrt_r(double x) { return rsqrt64(x); }
-__device__ __forceinline__ float rsqrt_r(float x) { return rsqrtf(x); }
+__device__ __forceinline__ float rsqrt_r(float x) { return rsqrt_fast(x); }
 __device__ __forceinline__ double rcp_r(double x) { return rcp64(x); }
 __device__ __forceinline__ float rcp_r(float x) { return rcpf(x); }
 __device__ __forceinline__ double sqrt_r(double x) { return sqrt64(x); }
@@ -324,7 +328,7 @@ __device__ __forceinline__ void locate(const DevGeom& g, const StepOrigin& O, fl
     // colatitude: angle from (z_i, rho_i) to (z_q, rho_q) in the meridional plane
     const float e = 2.0f * rd + dd;
     const float m = fmaxf(O.rho2 + e, 0.0f);
-    const float rhoi = m > 1.0e-24f ? rsqrtf(m) : 0.0f;  // 0 on the polar axis (rho < 1e-12)
+    const float rhoi = m > 1.0e-24f ? rsqrt_fast(m) : 0.0f;  // 0 on the polar axis (rho < 1e-12)
     const float rhoq = m * rhoi;
     const float den = rhoq + O.rho;
     const float zq = O.z + dz;
@@ -333,7 +337,7 @@ __device__ __forceinline__ void locate(const DevGeom& g, const StepOrigin& O, fl
     // so that rho_q - rho_i = e / (rho_q + rho_i) needs no division; on the
     // axis both parts vanish
     x1 = O.f1 + atan2_inc(O.z * e - O.rho * dz * den, den * (O.z * zq + O.rho * rhoq)) * g.inv_dth;
-    L.rinv = rsqrtf(O.r2 + c);
+    L.rinv = rsqrt_fast(O.r2 + c);
     L.rho = rhoq;
     L.axis = rhoq < 1e-12f;
     L.rhoinv = L.axis ? 0.0f : rhoi;
