@@ -42,11 +42,11 @@ VALU_PEAK_TFLOPS = 78.6
 # valid only for the kernel sources they were taken on (hash below); reported as
 # null as soon as those sources change.
 KERNEL_SOURCES = ("rt_trace.hpp", "rt_kernels.hip", "rt_internal.hpp")
-TRAFFIC = {"sources_sha256_16": "bb095f0cce73a318", "read_bytes": 2907551 * 1024 * 2.000,
-           "write_bytes": 15219 * 1024 * 1.000,
+TRAFFIC = {"sources_sha256_16": "eb8c8163f98b9b3a", "read_bytes": 2908415 * 1024 * 2.000,
+           "write_bytes": 15230 * 1024 * 1.000,
            # SQ_INSTS_VALU + 3 x SQ_INSTS_VALU_TRANS_F32 per ray-step (per lane) of
            # the same profile: the VALU issue slots of the compiled step
-           "valu_slots_per_ray_step": 2517}
+           "valu_slots_per_ray_step": 2458}
 # Model bytes one ray-step of this layout gathers (10 force evaluations x 8
 # corners x 16 B of (n_e, grad n_e) + one value evaluation x 8 x (4 B n_e + 4 B T)),
 # and the 448 B of a layout that stores n_e only and differentiates the corners.

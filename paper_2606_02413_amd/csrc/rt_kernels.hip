@@ -109,7 +109,7 @@ __global__ __launch_bounds__(256) void k_launch_table(TraceArgs a, double* out, 
       C.c = &lds_c[wave][0][lane];
       C.t = &lds_t[wave][0][lane];
       float ne, t;
-      eval_value<KIND>(a.g, a.models[m].nfg, a.models[m].te, C, O, 0.f, 0.f, 0.f, ne, t);
+      eval_value<KIND, true>(a.g, a.models[m].nfg, a.models[m].te, C, O, 0.f, 0.f, 0.f, ne, t);
       ne_out[size_t(m) * n + p] = ne;
     }
   }

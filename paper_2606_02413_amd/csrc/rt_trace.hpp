@@ -285,6 +285,7 @@ struct Loc {
   float u, v, w;
   // chain-rule pieces at the evaluation point (spherical)
   float rinv, rhoinv, rho, x, y, z;
+  float axz;           // z on the polar axis, else 0
   bool axis;
   bool cl0, cl1, cl2;  // index held at an edge along axis 0, 1, 2 (no dependence on position)
 };
@@ -314,10 +315,26 @@ __device__ __forceinline__ void cell_periodic(float x, int I, int n, int& c, flo
   if ((unsigned)c >= (unsigned)n) c = 0;
 }
 
-template <int KIND>
+// AT_ORIGIN: the point is r_i itself (d = 0), whose index is the origin's and
+// whose chain-rule pieces need no offset arithmetic (the same values as the
+// general form at d = 0).
+template <int KIND, bool AT_ORIGIN = false>
 __device__ __forceinline__ void locate(const DevGeom& g, const StepOrigin& O, float dx, float dy, float dz, Loc& L) {
   float x0, x1, x2;
-  if constexpr (KIND == RT_GRID_SPHERICAL_LOGR) {
+  if constexpr (AT_ORIGIN) {
+    x0 = O.f0; x1 = O.f1; x2 = O.f2;
+    if constexpr (KIND == RT_GRID_SPHERICAL_LOGR) {
+      const float m = fmaxf(O.rho2, 0.0f);
+      const float rhoi = m > 1.0e-24f ? rsqrt_fast(m) : 0.0f;
+      const float rhoq = m * rhoi;
+      L.rinv = rsqrt_fast(O.r2);
+      L.rho = rhoq;
+      L.axis = rhoq < 1e-12f;
+      L.rhoinv = L.axis ? 0.0f : rhoi;
+      L.x = O.x; L.y = O.y; L.z = O.z;
+      L.axz = L.axis ? O.z : 0.0f;
+    }
+  } else if constexpr (KIND == RT_GRID_SPHERICAL_LOGR) {
     // radius: |q|^2 = |r_i|^2 (1 + c / |r_i|^2), c = 2 r_i.d + |d|^2
     const float rd = O.x * dx + O.y * dy;
     const float dd = dx * dx + dy * dy;
@@ -342,6 +359,7 @@ __device__ __forceinline__ void locate(const DevGeom& g, const StepOrigin& O, fl
     L.axis = rhoq < 1e-12f;
     L.rhoinv = L.axis ? 0.0f : rhoi;
     L.x = O.x + dx; L.y = O.y + dy; L.z = zq;
+    L.axz = L.axis ? zq : 0.0f;
   } else {
     x0 = O.f0 + dx * g.inv_sp[0];
     x1 = O.f1 + dy * g.inv_sp[1];
@@ -367,12 +385,12 @@ __device__ __forceinline__ void weights8(float u, float v, float w, float W[8]) 
 // n_e and grad n_e [cm^-3 / R_sun] at r_i + d.  The gradient is the trilinear
 // interpolant of the per-vertex index-space gradient (continuous across cell
 // faces and clamped edges), mapped to Cartesian with the spherical unit vectors.
-template <int KIND>
+template <int KIND, bool AT_ORIGIN = false>
 __device__ __forceinline__ void eval_grad(const DevGeom& g, const float4* nfg, const float* te, CellCache& C,
                                           const StepOrigin& O, float dx, float dy, float dz, float& ne, float& gx,
                                           float& gy, float& gz) {
   Loc L;
-  locate<KIND>(g, O, dx, dy, dz, L);
+  locate<KIND, AT_ORIGIN>(g, O, dx, dy, dz, L);
   ensure_cell(g, nfg, te, C, L.key);
   float W[8];
   weights8(L.u, L.v, L.w, W);
@@ -399,7 +417,7 @@ __device__ __forceinline__ void eval_grad(const DevGeom& g, const float4* nfg, c
     const float A = G1 * (g.inv_dth * r2i);
     const float B = G2 * (g.inv_dph * (L.rhoinv * L.rhoinv));
     const float c = fmaf(A * L.z, L.rhoinv, grr);
-    gx = fmaf(L.x, c, -B * L.y) + (L.axis ? A * L.z : 0.0f);
+    gx = fmaf(A, L.axz, fmaf(L.x, c, -B * L.y));
     gy = fmaf(L.y, c, B * L.x);
     gz = fmaf(grr, L.z, -A * L.rho);
   } else {
@@ -410,11 +428,11 @@ __device__ __forceinline__ void eval_grad(const DevGeom& g, const float4* nfg, c
 }
 
 // n_e and T at r_i + d (values only).
-template <int KIND>
+template <int KIND, bool AT_ORIGIN = false>
 __device__ __forceinline__ void eval_value(const DevGeom& g, const float4* nfg, const float* te, CellCache& C,
                                            const StepOrigin& O, float dx, float dy, float dz, float& ne, float& t) {
   Loc L;
-  locate<KIND>(g, O, dx, dy, dz, L);
+  locate<KIND, AT_ORIGIN>(g, O, dx, dy, dz, L);
   ensure_cell(g, nfg, te, C, L.key);
   float W[8];
   weights8(L.u, L.v, L.w, W);
@@ -705,7 +723,7 @@ __device__ __forceinline__ void init_tube(const TraceArgs& a, RayState& R, CellC
   // the wavevector difference (n_j - n_0) d from the difference of n_e, so that
   // it is not lost in the rounding of n (n_j - n_0 = -Xf (ne_j - ne_0) / (n_j + n_0))
   float ne0, te0;
-  eval_value<KIND>(a.g, R.nfg, R.te, C, O, 0.f, 0.f, 0.f, ne0, te0);
+  eval_value<KIND, true>(a.g, R.nfg, R.te, C, O, 0.f, 0.f, 0.f, ne0, te0);
   const double xf = -2.0 * R.cfd;
   const double n0 = sqrt64(fmax(1.0 - xf * double(ne0), 0.0));
   for (int j = 0; j < 2; ++j) {
@@ -791,7 +809,7 @@ __device__ __forceinline__ int ray_step(const TraceArgs& a, RayStateT<S, typenam
   if (refr) {
     // Stage 1 at r_i also sets the step: dt = ds_max / max(n(r_i), n_floor).
     float ne, gx, gy, gz;
-    eval_grad<KIND>(a.g, R.nfg, R.te, C, O, 0.f, 0.f, 0.f, ne, gx, gy, gz);
+    eval_grad<KIND, true>(a.g, R.nfg, R.te, C, O, 0.f, 0.f, 0.f, ne, gx, gy, gz);
     F1x = R.cf * gx; F1y = R.cf * gy; F1z = R.cf * gz;
     sx = gx; sy = gy; sz = gz;
     tx = gx; ty = gy; tz = gz;
