@@ -56,12 +56,23 @@ def fit_params(cor_kw, n_pix, half, freqs, iters, lr, start, log=None, log_every
     parts = corona.structured_parts(device="cuda", **cor_kw)
     pc = ParamCorona(parts)
     shape = (cor_kw["nr"], cor_kw["nt"], cor_kw["nph"])
-    truth = pc.truth()
+    truth = pc.truth(cor_kw.get("t_bg", 1.2e6))
     th_true = torch.tensor(truth, dtype=torch.float64, device="cuda")
     ln_ne, ln_te = pc(th_true, shape)
     cor = corona.Corona(*shape, cor_kw["r_in"], cor_kw["r_max"], torch.exp(ln_ne).cpu().numpy(),
                         torch.exp(ln_te).cpu().numpy(), "param-truth")
     model = R.Model.from_corona(cor)
+    try:
+        theta, hist = _fit(pc, model, shape, n_pix, half, freqs, iters, lr, start, log, log_every, decay, polish,
+                           ln_ne, ln_te)
+    finally:
+        model.close()
+    return truth, hist, theta
+
+
+def _fit(pc, model, shape, n_pix, half, freqs, iters, lr, start, log, log_every, decay, polish, ln_ne, ln_te):
+    import torch
+    from . import rtsun as R
     im = R.image_desc(n_pix, half)
     prm = R.params(ds_max=0.01, n_floor=0.1)
     F = R.rtsun_function()
@@ -107,5 +118,4 @@ def fit_params(cor_kw, n_pix, half, freqs, iters, lr, start, log=None, log_every
                 record(iters + k, objective(), "lbfgs")
     with torch.no_grad():
         record(iters + polish, objective(), "final")
-    model.close()
-    return truth, hist, theta.detach().cpu().numpy()
+    return theta.detach().cpu().numpy(), hist

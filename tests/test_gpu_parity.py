@@ -152,6 +152,27 @@ def test_structured_ragged_image(R, orc, structured_small, adaptive):
         PU.compare(g["tb"][0, k].reshape(-1), g["info"][0, k].reshape(-1), o, label=f"ragged-{f/1e6:.0f}")
 
 
+@pytest.mark.parametrize("nu,nv", [(1, 1), (1, 9), (13, 1), (8, 8), (9, 8)])
+def test_degenerate_and_single_tile_images(R, orc, structured_small, nu, nv):
+    """Images of one pixel, one row or column (a tile that is mostly tail), one
+    exact 8x8 tile and one tile plus a one-column tail, through both launch
+    schedules, against the oracle on every pixel."""
+    cor, m = structured_small
+    kw = PU.step_kwargs(0.01, 0.1)
+    im_g = R.image_desc(nu, 1.7, nv=nv, half_v=1.3)
+    im_o = orc.make_image(nu, 1.7, nv=nv, half_v=1.3)
+    pix = np.arange(nu * nv, dtype=np.int32)
+    o = PU.oracle_trace(orc, cor, 90e6, nu, 1.7, pix, kw, image=im_o)
+    maps = []
+    for plain in (False, True):
+        print(f"case image {nu}x{nv} plain={plain}", flush=True)
+        g = PU.gpu_trace([m], [90e6], nu, 1.7, kw, image=im_g, plain=plain)
+        assert g["tb"].shape == (1, 1, nv, nu)
+        PU.compare(g["tb"].reshape(-1), g["info"].reshape(-1), o, label=f"image-{nu}x{nv}-{plain}")
+        maps.append(g["tb"])
+    assert np.array_equal(maps[0], maps[1])
+
+
 @pytest.mark.parametrize("obs_dir,up", [((0.3, -0.8, 0.52), (0.0, 0.0, 1.0)),
                                          ((0.3420201433, 0.0, 0.9396926208), (0.0, 1.0, 0.0))])
 def test_observer_directions(R, orc, structured_small, obs_dir, up):

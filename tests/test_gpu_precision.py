@@ -98,3 +98,56 @@ def test_precision_variants_are_distinct_kernels(R, case):
             (dict(), dict(fp32_step=True), dict(all_fp32=True))]
     assert not np.array_equal(maps[0], maps[1])
     assert not np.array_equal(maps[1], maps[2])
+
+
+@pytest.mark.parametrize("variant", ["fp32_step", "all_fp32"])
+def test_precision_variants_other_modes_and_grids(R, orc, variant):
+    """The FP32 variants in the reduced tracing modes (straight lines of sight,
+    refraction without the tube term) on a structured spherical model, and on a
+    Cartesian grid (a linear slab, the exact parabola case), against the
+    oracle: the same termination codes on every compared ray, and the loose
+    bars of the variants above."""
+    prm_kw = dict(all_fp32=variant == "all_fp32", fp32_step=variant == "fp32_step")
+    cor = corona.structured(nr=64, nt=32, nph=64, r_in=1.0, r_max=30.0, seed=11, n_ar=4, n_feat=256)
+    m = R.Model.from_corona(cor)
+    pix = np.arange(0, 32 * 32, 2, dtype=np.int32)
+    rels = []
+    try:
+        for refr, mag in ((False, False), (True, False)):
+            kw = PU.step_kwargs(0.01, 0.1, refraction=refr, magnification=mag)
+            print(f"case precision {variant} modes refraction={refr} magnification={mag}", flush=True)
+            g = PU.gpu_trace([m], [60e6], 32, 2.0, kw, **prm_kw)
+            o = PU.oracle_trace(orc, cor, 60e6, 32, 2.0, pix, kw)
+            info = g["info"].reshape(-1)[pix]
+            same = info["code"].astype(np.int32) == o["code"]
+            assert np.all(same | (o["flags"] != 0)), (refr, mag, int((~same).sum()))
+            tb = g["tb"].reshape(-1)[pix].astype(np.float64)
+            rels.append(np.abs(tb - o["tb"])[same] / np.maximum(np.abs(o["tb"][same]), PU.TB_FLOOR))
+            if not mag:
+                assert np.all(g["info"]["ln_s_end"] == 0)
+    finally:
+        m.close()
+    n = 25
+    k = np.arange(n)
+    ne = np.broadcast_to((1e6 + 5e4 * k)[None, None, :], (n, n, n)).astype(np.float32).copy()
+    te = np.full((n, n, n), 1e6, np.float32)
+    d = R.grid_desc(R.RT_GRID_CARTESIAN, (n, n, n), -1.0, 5.0, origin=(-6, -6, -6), spacing=(0.5, 0.5, 0.5))
+    mc = R.Model(d, ne, te)
+    try:
+        kw = PU.step_kwargs(0.01, 1.0)
+        print(f"case precision {variant} cartesian", flush=True)
+        g = PU.gpu_trace([mc], [20e6], 16, 3.0, kw, **prm_kw)
+    finally:
+        mc.close()
+    med = orc.OracleMedium(orc.GRID_CARTESIAN, shape=(n, n, n), r_in=-1.0, r_max=5.0, ne=ne, te=te,
+                           origin=(-6, -6, -6), spacing=(0.5, 0.5, 0.5))
+    o = orc.trace_pixels(med, orc.make_params(**kw), orc.make_image(16, 3.0), 20e6, np.arange(256, dtype=np.int32))
+    info = g["info"].reshape(-1)
+    same = info["code"].astype(np.int32) == o["code"]
+    assert np.all(same | (o["flags"] != 0)), int((~same).sum())
+    tb = g["tb"].reshape(-1).astype(np.float64)
+    rels.append(np.abs(tb - o["tb"])[same] / np.maximum(np.abs(o["tb"][same]), PU.TB_FLOOR))
+    for r, label in zip(rels, ("line of sight", "refraction without the tube term", "cartesian")):
+        print(f"precision {variant} {label}: max {r.max():.2e} median {np.median(r):.2e} ({r.size} rays)", flush=True)
+        assert np.median(r) < 1e-3, (variant, label)
+        assert r.max() < 5e-2, (variant, label)
