@@ -33,6 +33,8 @@
  *    adjoint workspace is freed when outgrown, and rt_trace_adjoint refuses
  *    graph capture).  A captured graph uses the tables of the stream it was
  *    captured on: replaying it while another call runs on that stream races.
+ *  - A call on a model makes the model's device the calling thread's current
+ *    HIP device (and leaves it so); rt_model_load makes `device` current.
  *  - Grid limits (RT_E_CAPACITY): n0 * n1 < 2^24, the packed row length
  *    (n2 + 1 for spherical grids, n2 for Cartesian) < 2^24, and
  *    n0 * n1 * (packed row length) <= 2^31 - 1.
