@@ -293,6 +293,37 @@ def test_structured_workload_full_size_sampled(R, orc):
     torch.cuda.empty_cache()
 
 
+def test_batched_workload_sampled(R, orc):
+    """The batched workload in the launch bench.py times: the structured model
+    with seeds 0-3, every 8th of its 64 frequencies (40-800 MHz), 1024^2 image
+    over +/-3 R_sun, all in one persistent launch; the oracle on 16 seeded
+    pixels of every (model, frequency) map, and the launch's step statistics
+    against the per-ray step counts."""
+    wl = corona.workload("batched")
+    freqs = wl.freqs[::8]
+    cors = wl.models(device="cuda")
+    models = [R.Model.from_corona(c) for c in cors]
+    kw = PU.step_kwargs(wl.ds_max, wl.n_floor, max_steps=wl.max_steps)
+    try:
+        print(f"case batched workload: {len(models)} models x {len(freqs)} frequencies x {wl.n_pix}^2", flush=True)
+        g = PU.gpu_trace(models, freqs, wl.n_pix, wl.half_width, kw)
+        assert g["tb"].shape == (len(models), len(freqs), wl.n_pix, wl.n_pix)
+        assert g["stats"]["ray_steps"] == int(g["info"]["n_steps"].astype(np.int64).sum())
+        pix = corona.seeded_pixels(wl.n_pix, 16, 3002)
+        n = flagged = 0
+        for mi, cor in enumerate(cors):
+            for k, f in enumerate(freqs):
+                o = PU.oracle_trace(orc, cor, f, wl.n_pix, wl.half_width, pix, kw)
+                s = PU.compare(g["tb"][mi, k].reshape(-1)[pix], g["info"][mi, k].reshape(-1)[pix], o,
+                               label=f"batched-model{mi}-{f/1e6:.0f}MHz")
+                n += s["n"]
+                flagged += s["flagged"]
+        assert flagged < 0.3 * n, (flagged, n)
+    finally:
+        for m in models:
+            m.close()
+
+
 def test_graph_replay_equals_eager(R, structured_small):
     """A captured trace call replayed several times, with eager work and
     synchronizations between replays, gives the eager maps every time."""
