@@ -241,6 +241,26 @@ class Model:
             pass
 
 
+def _out(res, key, shape, dtype, dev):
+    """res[key]: allocated when absent, else checked to be a contiguous tensor of
+    exactly this shape, dtype and device (the library writes through its raw
+    pointer)."""
+    import torch
+    t = res.get(key)
+    if t is None:
+        t = torch.empty(shape, dtype=dtype, device=dev)
+        res[key] = t
+    elif tuple(t.shape) != tuple(shape) or t.dtype != dtype or t.device != dev or not t.is_contiguous():
+        raise ValueError(f"out[{key!r}] must be a contiguous {dtype} tensor of shape {tuple(shape)} on {dev}")
+    return t
+
+
+def _handles(models):
+    if any(m.handle is None for m in models):
+        raise ValueError("a model was closed")
+    return (C.c_void_p * len(models))(*[m.handle.value for m in models])
+
+
 def trace_maps(models, freqs, image, prm, *, info=True, stats=True, path_rays=None, path_capacity=0,
                stream=None, out=None):
     """Trace all (model, frequency) maps.  Returns a dict of torch tensors on the device:
@@ -254,13 +274,12 @@ def trace_maps(models, freqs, image, prm, *, info=True, stats=True, path_rays=No
     dev = torch.device("cuda", models[0].device)
     shape = (M, F, image.nv, image.nu)
     res = {} if out is None else out
-    if "tb" not in res:
-        res["tb"] = torch.empty(shape, dtype=torch.float32, device=dev)
-    if info and "info" not in res:
-        res["info"] = torch.empty(shape + (32,), dtype=torch.uint8, device=dev)
-    if stats and "stats" not in res:
-        res["stats"] = torch.empty(40, dtype=torch.uint8, device=dev)
-    handles = (C.c_void_p * M)(*[m.handle.value for m in models])
+    _out(res, "tb", shape, torch.float32, dev)
+    if info:
+        _out(res, "info", shape + (32,), torch.uint8, dev)
+    if stats:
+        _out(res, "stats", (40,), torch.uint8, dev)
+    handles = _handles(models)
     n_path = 0
     pr = None
     if path_rays is not None and len(path_rays) > 0:
@@ -358,14 +377,24 @@ def beam_fwhm(freqs, baseline_m):
     return out
 
 
+def _check_maps(maps, image):
+    import torch
+    if maps.dtype != torch.float32 or not maps.is_cuda or maps.dim() < 2 or \
+            tuple(maps.shape[-2:]) != (image.nv, image.nu):
+        raise ValueError(f"maps must be a float32 device tensor [..., {image.nv}, {image.nu}]")
+
+
 def beam_convolve(maps, image, fwhm, *, stream=None, out=None):
     """Maps [..., nv, nu] (float32 device tensor) convolved with Gaussian beams of
     the given FWHM (R_sun, one per map in the flattened leading dimensions)."""
     import torch
+    _check_maps(maps, image)
     x = maps.contiguous()
     n_maps = x.numel() // (image.nu * image.nv)
     fw = np.ascontiguousarray(np.broadcast_to(np.asarray(fwhm, dtype=np.float64), (n_maps,)))
     y = torch.empty_like(x) if out is None else out
+    if y.shape != x.shape or y.dtype != x.dtype or y.device != x.device or not y.is_contiguous():
+        raise ValueError("out must be a contiguous tensor of the maps' shape, dtype and device")
     _check(lib().rt_beam_convolve(C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()), n_maps, image.nu, image.nv,
                                   image.half_u, image.half_v, fw.ctypes.data_as(C.POINTER(C.c_double)),
                                   _stream_ptr(stream)))
@@ -376,6 +405,7 @@ def disc_mean(maps, image, radius=0.5, *, stream=None):
     """Mean T_b within `radius` R_sun of the image centre of each map [..., nv, nu]
     (float64 device tensor of the leading shape)."""
     import torch
+    _check_maps(maps, image)
     x = maps.contiguous()
     lead = x.shape[:-2]
     n_maps = x.numel() // (image.nu * image.nv)
@@ -442,13 +472,12 @@ def trace_maps_static(models, freqs, image, prm, *, info=True, stats=True, strea
     dev = torch.device("cuda", models[0].device)
     shape = (M, F, image.nv, image.nu)
     res = {} if out is None else out
-    if "tb" not in res:
-        res["tb"] = torch.empty(shape, dtype=torch.float32, device=dev)
-    if info and "info" not in res:
-        res["info"] = torch.empty(shape + (32,), dtype=torch.uint8, device=dev)
-    if stats and "stats" not in res:
-        res["stats"] = torch.empty(40, dtype=torch.uint8, device=dev)
-    handles = (C.c_void_p * M)(*[m.handle.value for m in models])
+    _out(res, "tb", shape, torch.float32, dev)
+    if info:
+        _out(res, "info", shape + (32,), torch.uint8, dev)
+    if stats:
+        _out(res, "stats", (40,), torch.uint8, dev)
+    handles = _handles(models)
     ptr = lambda k: C.c_void_p(res[k].data_ptr()) if k in res and res[k] is not None else C.c_void_p(0)
     _check(lib().rt_trace_maps_static(handles, M, freqs.ctypes.data_as(C.POINTER(C.c_double)), F, C.byref(image),
                                       C.byref(prm), ptr("tb"), ptr("info") if info else C.c_void_p(0),
@@ -460,14 +489,20 @@ class CapturedTrace:
     """A captured rt_trace_maps call: `replay()` re-runs the whole call (counter
     and statistics fills, the launch table and the trace kernels) into the
     tensors of `out`.  The graph was captured on `stream`, a stream of its own,
-    whose library tables it uses; the object keeps that stream alive."""
+    whose library tables it uses; the object keeps that stream and the models
+    alive.  The graph reads the models' device arrays: replaying after a model
+    was closed raises, and rt_model_update between replays changes what the
+    next replay traces."""
 
-    def __init__(self, graph, out, stream):
+    def __init__(self, graph, out, stream, models):
         self.graph = graph
         self.out = out
         self.stream = stream
+        self.models = list(models)
 
     def replay(self):
+        if any(m.handle is None for m in self.models):
+            raise RuntimeError("a model of this captured trace was closed")
         self.graph.replay()
 
 
@@ -488,7 +523,7 @@ def capture_trace_maps(models, freqs, image, prm, *, info=False, stats=True):
     with torch.cuda.graph(graph, stream=stream):
         trace_maps(models, freqs, image, prm, info=info, stats=stats, out=out)
     torch.cuda.current_stream().wait_stream(stream)
-    return CapturedTrace(graph, out, stream), out
+    return CapturedTrace(graph, out, stream, models), out
 
 
 def trace_adjoint(model, freqs, image, prm, weights, *, tb=True, stream=None, out=None):
@@ -503,17 +538,16 @@ def trace_adjoint(model, freqs, image, prm, weights, *, tb=True, stream=None, ou
     dev = torch.device("cuda", model.device)
     if tuple(weights.shape) != (F, image.nv, image.nu) or weights.dtype != torch.float32:
         raise ValueError("weights must be float32 [n_freq][nv][nu]")
-    if not weights.is_contiguous():
-        raise ValueError("weights must be contiguous")
+    if not weights.is_contiguous() or weights.device != dev:
+        raise ValueError(f"weights must be contiguous and on {dev}")
+    if model.handle is None:
+        raise ValueError("the model was closed")
     res = {} if out is None else out
-    if "loss" not in res:
-        res["loss"] = torch.empty(1, dtype=torch.float64, device=dev)
-    if "grad_ln_ne" not in res:
-        res["grad_ln_ne"] = torch.empty(model.shape, dtype=torch.float32, device=dev)
-    if "grad_ln_te" not in res:
-        res["grad_ln_te"] = torch.empty(model.shape, dtype=torch.float32, device=dev)
-    if tb and "tb" not in res:
-        res["tb"] = torch.empty((F, image.nv, image.nu), dtype=torch.float32, device=dev)
+    _out(res, "loss", (1,), torch.float64, dev)
+    _out(res, "grad_ln_ne", tuple(model.shape), torch.float32, dev)
+    _out(res, "grad_ln_te", tuple(model.shape), torch.float32, dev)
+    if tb:
+        _out(res, "tb", (F, image.nv, image.nu), torch.float32, dev)
     ptr = lambda k: C.c_void_p(res[k].data_ptr())
     _check(lib().rt_trace_adjoint(model.handle, freqs.ctypes.data_as(C.POINTER(C.c_double)), F, C.byref(image),
                                   C.byref(prm), C.c_void_p(weights.data_ptr()), ptr("loss"), ptr("grad_ln_ne"),

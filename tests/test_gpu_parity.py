@@ -350,6 +350,21 @@ def test_graph_replay_equals_eager(R, structured_small):
         assert float(junk) == float(junk)
 
 
+def test_graph_refuses_replay_after_its_model_is_closed(R):
+    """A captured trace keeps its models; once one is closed (its device arrays
+    freed), replay raises instead of launching kernels that would read them."""
+    import torch
+    cor = corona.spherically_symmetric()
+    m = R.Model.from_corona(cor)
+    print("case graph after model close", flush=True)
+    cap, out = R.capture_trace_maps([m], [150e6], R.image_desc(16, 2.5), R.params())
+    cap.replay()
+    torch.cuda.synchronize()
+    m.close()
+    with pytest.raises(RuntimeError, match="closed"):
+        cap.replay()
+
+
 def test_graph_survives_larger_calls_on_its_stream(R, structured_small):
     """Calls larger than a captured one grow the library's tables of that
     stream; the outgrown tables are retired, not freed, so the graph's replays
