@@ -607,8 +607,10 @@ def gradcheck_study(n_pixels=64, n_cells=200, h=1e-3):
     the oracle's forward loss at ln value +-h (the FP32 value e^{+-h} x, the
     difference divided by the realized ln difference), against the adjoint and
     the tape gradient.  Each FD outlier is checked for a discrete event in the
-    oracle between +h and -h (a changed step count or termination code) and for
-    the FD's own non-smoothness (FD at h/2 against FD at h)."""
+    oracle between +h and -h (a changed step count or termination code, or a
+    changed cell, edge clamp or branch of any evaluation: the oracle's record of
+    the ray's discrete decisions) and for the FD's own non-smoothness (FD at h/2
+    against FD at h)."""
     import torch
     from oracle import oracle as O
     from paper_2606_02413_amd import corona, rtsun as R
@@ -647,13 +649,17 @@ def gradcheck_study(n_pixels=64, n_cells=200, h=1e-3):
     sel_pix = np.asarray(pix, dtype=np.int32)
 
     def loss_of(med_x):
+        """Loss of the FP64 forward on the weighted rays; per ray the step count,
+        code and the record of every discrete decision (weighted rays only)."""
         tot = 0.0
-        info = []
+        info, events = [], []
         for k, f in enumerate(freqs):
             r = O.trace_pixels(med_x, O.make_params(**kw), imo, f, sel_pix)
             tot += float((w[k].flat[sel_pix].astype(np.float64) * r["tb"]).sum())
-            info.append(np.stack([r["n_steps"], r["code"]]))
-        return tot, np.stack(info)
+            weighted = w[k].flat[sel_pix] != 0
+            info.append(np.stack([np.where(weighted, r["n_steps"], 0), np.where(weighted, r["code"], 0)]))
+            events.append(np.where(weighted, r["event_hash"], np.uint64(0)))
+        return tot, np.stack(info), np.stack(events)
 
     fields = []
     for name, g_orc, g_gpu, arr in (("ln_ne", gne_o, gne, cor.ne), ("ln_te", gte_o, gte, cor.te)):
@@ -670,27 +676,31 @@ def gradcheck_study(n_pixels=64, n_cells=200, h=1e-3):
             def fd(hh):
                 xp, xm = np.float32(x0 * np.exp(hh)), np.float32(x0 * np.exp(-hh))
                 flat[v] = xp
-                lp, ip = loss_of(O.OracleMedium.from_corona(cor))
+                lp, ip, ep = loss_of(O.OracleMedium.from_corona(cor))
                 flat[v] = xm
-                lm, im_ = loss_of(O.OracleMedium.from_corona(cor))
+                lm, im_, em = loss_of(O.OracleMedium.from_corona(cor))
                 flat[v] = x0
-                return (lp - lm) / (np.log(np.float64(xp)) - np.log(np.float64(xm))), bool(np.array_equal(ip, im_))
+                return ((lp - lm) / (np.log(np.float64(xp)) - np.log(np.float64(xm))), bool(np.array_equal(ip, im_)),
+                        bool(np.array_equal(ep, em)))
 
-            d1, same1 = fd(h)
+            d1, same1, smooth1 = fd(h)
             go, gg = float(g_orc.reshape(-1)[v]), float(g_gpu.reshape(-1)[v])
             row = {"vertex": int(v), "fd": d1, "tape": go, "adjoint": gg,
                    "adjoint_vs_fd": abs(gg - d1) / abs(d1) if d1 != 0 else float("inf"),
                    "tape_vs_fd": abs(go - d1) / abs(d1) if d1 != 0 else float("inf"),
-                   "steps_and_codes_unchanged": same1}
+                   "steps_and_codes_unchanged": same1,
+                   # no discrete decision of any weighted ray differs between +h and -h
+                   "no_discrete_event": smooth1}
             if row["adjoint_vs_fd"] > 1e-4:
                 # is the difference the FD's own (kinks of the piecewise-trilinear
                 # discrete map within +-h)?  FD at smaller h, against the adjoint
-                d2, same2 = fd(0.5 * h)
+                d2, same2, _ = fd(0.5 * h)
                 row["fd_half_h"] = d2
                 row["fd_h_vs_half_h"] = abs(d1 - d2) / abs(d2) if d2 != 0 else float("inf")
                 row["adjoint_vs_fd_half_h"] = abs(gg - d2) / abs(d2) if d2 != 0 else float("inf")
                 for hs in (1e-4, 1e-5):
-                    ds_, _ = fd(hs)
+                    ds_, _, sm_ = fd(hs)
+                    row[f"no_discrete_event_{hs:g}"] = sm_
                     row[f"adjoint_vs_fd_{hs:g}"] = abs(gg - ds_) / abs(ds_) if ds_ != 0 else float("inf")
                     row[f"tape_vs_fd_{hs:g}"] = abs(go - ds_) / abs(ds_) if ds_ != 0 else float("inf")
             rows.append(row)
@@ -705,8 +715,17 @@ def gradcheck_study(n_pixels=64, n_cells=200, h=1e-3):
             v = [r[f"adjoint_vs_fd_{hs:g}"] for r in outl]
             conv[f"outliers_within_1e-4_at_h_{hs:g}"] = int(sum(x <= 1e-4 for x in v))
             conv[f"outliers_median_adjoint_vs_fd_at_h_{hs:g}"] = float(np.median(v)) if v else 0.0
+        # every outlier at h: a discrete event within +-h (the difference spans a
+        # kink of the piecewise-smooth traced map), or none (unexplained)
+        events = {"outliers": len(outl),
+                  "with_step_or_code_change": int(sum(not r["steps_and_codes_unchanged"] for r in outl)),
+                  "with_cell_or_branch_change_only": int(sum(r["steps_and_codes_unchanged"] and not r["no_discrete_event"]
+                                                             for r in outl)),
+                  "without_discrete_event": int(sum(r["no_discrete_event"] for r in outl)),
+                  "vertices_without_event_at_h": int(sum(r["no_discrete_event"] for r in rows)),
+                  "within_1e-4_of_those": int(sum(r["no_discrete_event"] and r["adjoint_vs_fd"] <= 1e-4 for r in rows))}
         fields.append({"field": name, "cells": len(rows), "fraction_within_1e-4": float(np.mean(within)),
-                       "outlier_convergence": conv,
+                       "outlier_events": events, "outlier_convergence": conv,
                        # within 1e-4 at h, or else at one of the smaller h
                        "fraction_within_1e-4_any_h": float(np.mean(
                            [min(r["adjoint_vs_fd"], r.get("adjoint_vs_fd_0.0001", 1.0),
@@ -715,7 +734,7 @@ def gradcheck_study(n_pixels=64, n_cells=200, h=1e-3):
                        "median_adjoint_vs_fd": float(np.median([r["adjoint_vs_fd"] for r in rows])),
                        "outliers": outl, "fd_seconds": round(t_fd, 1)})
         progress(f"gradcheck {name}: {fields[-1]['fraction_within_1e-4']:.3f} within 1e-4, "
-                 f"{len(outl)} outliers, {t_fd:.0f} s")
+                 f"{len(outl)} outliers ({events['without_discrete_event']} without a discrete event), {t_fd:.0f} s")
     out["fd"] = fields
     print(json.dumps(out), flush=True)
 

@@ -75,13 +75,14 @@ class Result(C.Structure):
     _fields_ = [("tb", C.c_double), ("tau", C.c_double), ("ln_s_end", C.c_double), ("r_min", C.c_double),
                 ("exit_pos", C.c_double * 3), ("lam_last", C.c_double),
                 ("bouguer_drift", C.c_double), ("ham_drift", C.c_double), ("ln_s_min", C.c_double),
-                ("twin_dexit", C.c_double), ("n_steps", C.c_int32), ("code", C.c_int32), ("flags", C.c_int32), ("_pad", C.c_int32)]
+                ("twin_dexit", C.c_double), ("n_steps", C.c_int32), ("code", C.c_int32), ("flags", C.c_int32), ("_pad", C.c_int32),
+                ("event_hash", C.c_uint64)]
 
 
 RESULT_DTYPE = np.dtype([("tb", "f8"), ("tau", "f8"), ("ln_s_end", "f8"), ("r_min", "f8"),
                          ("exit_pos", "f8", (3,)), ("lam_last", "f8"), ("bouguer_drift", "f8"),
                          ("ham_drift", "f8"), ("ln_s_min", "f8"), ("twin_dexit", "f8"), ("n_steps", "i4"), ("code", "i4"), ("flags", "i4"),
-                         ("_pad", "i4")])
+                         ("_pad", "i4"), ("event_hash", "u8")])
 assert RESULT_DTYPE.itemsize == C.sizeof(Result)
 
 _lib = None

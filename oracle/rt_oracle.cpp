@@ -223,6 +223,7 @@ struct Result {
   double ln_s_min;             // smallest ln(S/S_0) over the step points (0 at the start)
   double twin_dexit;           // exit movement of the twin ray [R_sun]; -1 if no twin was traced, +inf if its code differs
   int32_t n_steps, code, flags, _pad;
+  uint64_t event_hash;         // hash of the ray's discrete decisions (orc_trace_pixels; 0 elsewhere)
 };
 
 constexpr int kPathStride = 12;  // x y z s lnM dlnS/ds tau_cum ne_m te_m dtau gamma dt
@@ -262,6 +263,25 @@ template <class S> struct Sample {
   V3<S> grad;   // grad n_e [cm^-3 / R_sun]
   S te;
 };
+
+// Record of a ray's discrete decisions (a diagnostic; no arithmetic depends on
+// it): while a ray is traced for orc_trace_pixels, every medium evaluation adds
+// its cell and edge clamps, and every step its step-floor branch, the reference
+// axis of the basis and the sign of the area's triple product, to a running
+// FNV-1a hash.  Two traces with equal hashes took the same discrete path, so
+// along a continuous change of the model between them the traced map is smooth.
+inline uint64_t*& event_hash_ref() {
+  static thread_local uint64_t* h = nullptr;
+  return h;
+}
+inline void event_mix(uint64_t v) {
+  uint64_t* h = event_hash_ref();
+  if (!h) return;
+  for (int k = 0; k < 8; ++k) {
+    *h ^= (v >> (8 * k)) & 0xffu;
+    *h *= 0x100000001b3ull;
+  }
+}
 
 // Clamp a continuous index to [0, n-1]; report whether it was outside.
 template <class S> S clamp_index(const S& xi, int n, bool& clamped) {
@@ -326,6 +346,8 @@ Sample<S> eval_medium(const Medium& m, const Src& src, const V3<S>& pos, bool wa
       int c = int(std::floor(val(xp)));
       S u = xr - S(double(a)), v = xt - S(double(b)), w = xp - S(double(c));
       c = ((c % np) + np) % np;
+      event_mix((uint64_t(uint32_t(a)) << 42) ^ (uint64_t(uint32_t(b)) << 21) ^ uint64_t(uint32_t(c)) ^
+                (uint64_t(cr) << 61) ^ (uint64_t(ct) << 62) ^ (uint64_t(on_axis) << 63));
       auto at = [&](int i, int j, int k) -> size_t {
         return (size_t(i) * nt + size_t(j)) * np + size_t(((k % np) + np) % np);
       };
@@ -384,6 +406,9 @@ Sample<S> eval_medium(const Medium& m, const Src& src, const V3<S>& pos, bool wa
         base[k] = std::min(int(std::floor(val(xi[k]))), n[k] - 2);
         fr[k] = xi[k] - S(double(base[k]));
       }
+      event_mix((uint64_t(uint32_t(base[0])) << 42) ^ (uint64_t(uint32_t(base[1])) << 21) ^
+                uint64_t(uint32_t(base[2])) ^ (uint64_t(cl[0]) << 61) ^ (uint64_t(cl[1]) << 62) ^
+                (uint64_t(cl[2]) << 63));
       auto at = [&](int i, int j, int k) -> size_t { return (size_t(i) * n[1] + size_t(j)) * n[2] + size_t(k); };
       auto diff = [&](int ax, int i, int j, int k) -> S {
         int id[3] = {i, j, k};
@@ -579,6 +604,7 @@ RayOut<S> trace_rk4(const Medium& m, const Src& src, const Params& P, double f,
       Sample<S> si = eval_medium(m, src, r, false);
       S ni = index_from_ne(si.ne, xf);
       dt = (val(ni) > P.n_floor) ? S(P.ds_max) / ni : S(P.ds_max / P.n_floor);
+      event_mix(val(ni) > P.n_floor ? 1u : 2u);
     } else {
       dt = S(P.ds_max);
     }
@@ -603,6 +629,7 @@ RayOut<S> trace_rk4(const Medium& m, const Src& src, const Params& P, double f,
     } else if (mag) {
       // Reference axis least aligned with t: z unless |t_z| is close to 1.
       V3<S> a = (std::fabs(val(that.z)) > 0.9) ? V3<S>{S(0.0), S(1.0), S(0.0)} : V3<S>{S(0.0), S(0.0), S(1.0)};
+      event_mix(std::fabs(val(that.z)) > 0.9 ? 3u : 4u);
       V3<S> c1 = cross(a, that);                          // Eq. 6
       V3<S> e1 = (S(1.0) / norm(c1)) * c1;
       V3<S> e2 = cross(that, e1);
@@ -613,6 +640,7 @@ RayOut<S> trace_rk4(const Medium& m, const Src& src, const Params& P, double f,
       rk4_step(m, src, xf, refr, dt, rb, pb);
       V3<S> d1 = ra - r1, d2 = rb - r1;                   // Eq. 9
       S area = fabs(dot(cross(d1, d2), that));            // Eq. 10 without the 1/2
+      event_mix(val(dot(cross(d1, d2), that)) < 0.0 ? 5u : 6u);
       S M = area / (eps * eps);                           // Eq. 11
       lnM = log(M);
     }
@@ -874,6 +902,7 @@ static void fill_result(const RayOut<double>& ro, Result& r) {
   r.lam_last = ro.lam_last; r.n_steps = ro.n_steps; r.code = ro.code; r.flags = ro.flags;
   r.bouguer_drift = ro.bouguer_drift; r.ham_drift = ro.ham_drift; r.ln_s_min = ro.ln_s_min; r._pad = 0;
   r.twin_dexit = -1.0;
+  r.event_hash = 0;
 }
 
 static RayOut<double> trace_any(const Medium& m, const Params& P, double f, const V3<double>& r0,
@@ -975,8 +1004,13 @@ int orc_trace_pixels(const Medium* m, const Params* P, const Image* im, double f
       r.r_min = L.b; r.lam_last = 1.0;
       return;
     }
+    uint64_t hash = 0xcbf29ce484222325ull;
+    event_hash_ref() = &hash;
     RayOut<double> ro = trace_any(*m, *P, freq, L.r0, L.dir, nullptr, 0, nullptr);
+    event_hash_ref() = nullptr;
     fill_result(ro, r);
+    hash ^= (uint64_t(uint32_t(ro.n_steps)) << 8) ^ uint64_t(uint32_t(ro.code));
+    r.event_hash = hash;
     r.flags |= grazing_flags(*m, *P, *im, freq, ju, iv, ro, &r.twin_dexit);
   });
   return 0;
