@@ -324,6 +324,64 @@ def test_batched_workload_sampled(R, orc):
             m.close()
 
 
+def test_vacuum_model(R, orc):
+    """n_e = 0 everywhere (a degenerate model the method allows): n = 1, so
+    every ray is a straight chord with M = 1 at every step and no absorption;
+    T_b is the boundary brightness behind it (tb_inner for chords that meet
+    r_in, i.e. impact parameter b < r_in; tb_sky otherwise), ln S_end = 0, and
+    the GPU matches the oracle ray by ray."""
+    import torch
+    nr, nt, nph = 16, 8, 16
+    ne = np.zeros((nr, nt, nph), np.float32)
+    te = np.full((nr, nt, nph), 1e6, np.float32)
+    m = R.Model(R.grid_desc(R.RT_GRID_SPHERICAL_LOGR, (nr, nt, nph), 1.0, 3.0), ne, te)
+    kw = PU.step_kwargs(0.01, 1.0, tb_inner=1e4, tb_sky=0.0)
+    print("case vacuum model", flush=True)
+    try:
+        g = PU.gpu_trace([m], [100e6], 16, 2.5, kw)
+    finally:
+        m.close()
+    tb = g["tb"].reshape(-1)
+    info = g["info"].reshape(-1)
+    u = -2.5 + (np.arange(16) + 0.5) * 5.0 / 16
+    b = np.sqrt(u[None, :] ** 2 + u[:, None] ** 2).reshape(-1)
+    hit = b < 1.0
+    assert np.all(info["code"][hit] == 2) and np.all(tb[hit] == np.float32(1e4))
+    traced = (~hit) & (b < 3.0)
+    assert np.all(info["code"][traced] == 1) and np.all(tb[traced] == 0.0)
+    assert np.max(np.abs(info["ln_s_end"][info["code"] != 3])) < 1e-9
+    med = orc.OracleMedium(orc.GRID_SPHERICAL_LOGR, shape=(nr, nt, nph), r_in=1.0, r_max=3.0, ne=ne, te=te)
+    o = orc.trace_pixels(med, orc.make_params(**kw), orc.make_image(16, 2.5), 100e6, np.arange(256, dtype=np.int32))
+    PU.compare(tb, info, o, label="vacuum")
+
+
+def test_call_capacity_limits(R, structured_small):
+    """The largest call shapes: 16 models and 128 frequencies in one persistent
+    launch give bitwise the maps of single-model, single-frequency calls; one
+    model or frequency more is refused before any device work."""
+    import torch
+    cor, m = structured_small
+    prm = R.params(ds_max=0.01, n_floor=0.1)
+    im = R.image_desc(8, 2.0)
+    freqs = corona.log_freqs(128)
+    print("case 128 frequencies in one call", flush=True)
+    many = R.trace_maps([m], freqs, im, prm, info=False, stats=False)["tb"]
+    for k in (0, 37, 127):
+        one = R.trace_maps([m], [freqs[k]], im, prm, info=False, stats=False)["tb"]
+        assert torch.equal(many[0, k], one[0, 0]), k
+    print("case 16 models in one call", flush=True)
+    m16 = R.trace_maps([m] * 16, [90e6, 300e6], im, prm, info=False, stats=False)["tb"]
+    one = R.trace_maps([m], [90e6, 300e6], im, prm, info=False, stats=False)["tb"]
+    for j in range(16):
+        assert torch.equal(m16[j], one[0]), j
+    with pytest.raises(R.RtError) as e:
+        R.trace_maps([m] * 17, [90e6], im, prm, info=False, stats=False)
+    assert e.value.status == 6
+    with pytest.raises(R.RtError) as e:
+        R.trace_maps([m], corona.log_freqs(129), im, prm, info=False, stats=False)
+    assert e.value.status == 6
+
+
 def test_graph_replay_equals_eager(R, structured_small):
     """A captured trace call replayed several times, with eager work and
     synchronizations between replays, gives the eager maps every time."""
