@@ -102,6 +102,34 @@ def test_gradient_matches_oracle_small(R, orc, small, mode):
     _compare_grad(f"{mode} ln_te", gte, gte_o)
 
 
+@pytest.mark.parametrize("eta,tb_inner,tb_sky", [(1e-1, 3e4, 5e3), (1e-3, 1e4, 0.0)])
+def test_gradient_matches_oracle_boundary_and_eta(R, orc, small, eta, tb_inner, tb_sky):
+    """Boundary brightness behind the rays (tb_inner, tb_sky: the transmittance
+    of the whole ray then enters the loss) and the perturbation ratio eta away
+    from their defaults, through the full method's adjoint."""
+    cor, m = small
+    freqs = np.array([60e6, 400e6])
+    print(f"case adjoint eta {eta} tb_inner {tb_inner} tb_sky {tb_sky}", flush=True)
+    med = orc.OracleMedium.from_corona(cor)
+    kw = dict(ds_max=0.01, n_floor=0.1, max_steps=200000, eta=eta, tb_inner=tb_inner, tb_sky=tb_sky)
+    im_o = orc.make_image(16, 2.0)
+    flags = _oracle_flags(orc, med, orc.make_params(twin_check=True, **kw), im_o, freqs, 256)
+    w = _weights((2, 16, 16), 1001, flags)
+    lo, gne_o, gte_o = orc.grad_loss(med, orc.make_params(**kw), im_o, freqs, w)
+    loss, gne, gte, tb = _run(R, m, freqs, R.image_desc(16, 2.0), R.params(**kw), w)
+    assert loss == pytest.approx(lo, rel=1e-5)
+    # The adjoint of a perturbed ray's force difference is the difference of
+    # FP32 trilinear weights at two points eps = eta ds apart, i.e. eps / (r dl)
+    # of a cell: with weights resolved to ~6e-8, its relative error is about
+    # 6e-8 r_in dl / (eta ds_max) (3e-5 at the default eta = 1e-2, 3e-4 at
+    # 1e-3; the oracle forms it in FP64).  The bar is twice that, and at
+    # least the common 1e-4.
+    dl = np.log(5.0 / 1.0) / 31
+    tol = max(GRAD_TOL, 2.0 * 6e-8 * 1.0 * dl / (eta * 0.01))
+    _compare_grad(f"eta {eta} ln_ne", gne, gne_o, tol=tol, l2_tol=tol)
+    _compare_grad(f"eta {eta} ln_te", gte, gte_o)
+
+
 def test_gradient_matches_oracle_polar_observer(R, orc, small):
     """Observer 20 degrees from the polar axis: the chords have |t_z| > 0.9 and
     take the y reference axis of Eq. 6, whose adjoint the default view never uses."""
