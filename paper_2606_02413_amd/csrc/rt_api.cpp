@@ -174,6 +174,7 @@ struct rt_model {
   float* raw_ne;  // staging copies of the input arrays (C-order)
   float* raw_te;
   size_t raw_bytes;
+  int* bad;       // invalid-value counter of device-side updates
 };
 
 namespace {
@@ -265,7 +266,8 @@ void free_model_memory(rt_model* m) {
   dev_free(m->te, m->te_bytes);
   dev_free(m->raw_ne, m->raw_bytes);
   dev_free(m->raw_te, m->raw_bytes);
-  m->nfg = nullptr; m->te = nullptr; m->raw_ne = nullptr; m->raw_te = nullptr;
+  dev_free(m->bad, sizeof(int));
+  m->nfg = nullptr; m->te = nullptr; m->raw_ne = nullptr; m->raw_te = nullptr; m->bad = nullptr;
 }
 
 
@@ -509,6 +511,7 @@ rt_status rt_model_load(const rt_grid_desc* desc, const float* ne, const float* 
     if (st == RT_OK) st = dev_alloc((void**)&m->te, m->te_bytes, "model T");
     if (st == RT_OK) st = dev_alloc((void**)&m->raw_ne, m->raw_bytes, "model staging n_e");
     if (st == RT_OK) st = dev_alloc((void**)&m->raw_te, m->raw_bytes, "model staging T");
+    if (st == RT_OK) st = dev_alloc((void**)&m->bad, sizeof(int), "validation counter");
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
     if (st == RT_OK) st = hip_check(hipMemcpyAsync(m->raw_ne, ne, m->raw_bytes, hipMemcpyHostToDevice, s), "copy n_e");
     if (st == RT_OK) st = hip_check(hipMemcpyAsync(m->raw_te, te, m->raw_bytes, hipMemcpyHostToDevice, s), "copy T");
@@ -549,15 +552,13 @@ rt_status rt_model_update(rt_model* m, const float* ne, const float* te, int32_t
         ne = m->raw_ne;
         te = m->raw_te;
       }
-      int* bad = nullptr;
-      st = dev_alloc((void**)&bad, sizeof(int), "validation counter");
-      if (st != RT_OK) return st;
+      // (the model's own counter: no allocation, and so no device-wide
+      // synchronisation of a free, in a fitting loop)
       int hbad = 0;
-      st = hip_check(launch_fill_u32(reinterpret_cast<unsigned*>(bad), 0u, 1, s), "fill");
-      if (st == RT_OK) st = hip_check(launch_validate(ne, te, n, bad, s), "validate kernel");
-      if (st == RT_OK) st = hip_check(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, s), "copy count");
+      st = hip_check(launch_fill_u32(reinterpret_cast<unsigned*>(m->bad), 0u, 1, s), "fill");
+      if (st == RT_OK) st = hip_check(launch_validate(ne, te, n, m->bad, s), "validate kernel");
+      if (st == RT_OK) st = hip_check(hipMemcpyAsync(&hbad, m->bad, sizeof(int), hipMemcpyDeviceToHost, s), "copy count");
       if (st == RT_OK) st = hip_check(hipStreamSynchronize(s), "validate sync");
-      dev_free(bad, sizeof(int));
       if (st != RT_OK) return st;
       if (hbad != 0)
         return fail(RT_E_NONFINITE_INPUT, std::to_string(hbad) + " model values are not finite or out of range");
