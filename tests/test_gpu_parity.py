@@ -57,13 +57,18 @@ def test_small_workload_frequencies(R, orc, small_model, freq):
     PU.compare(g["tb"].reshape(-1)[pix], g["info"].reshape(-1)[pix], o, label=f"small-{freq/1e6:.0f}MHz")
 
 
-def test_persistent_equals_plain_bitwise(R, structured_small):
+@pytest.mark.parametrize("variant", ["full", "no-magnification", "line-of-sight", "fp32-step", "all-fp32"])
+def test_persistent_equals_plain_bitwise(R, structured_small, variant):
+    """Both launch forms run the same per-ray code: bitwise equal maps, ray
+    records and step totals in every tracing mode and precision variant."""
     cor, m = structured_small
-    kw = PU.step_kwargs(0.01, 0.1)
+    kw = PU.step_kwargs(0.01, 0.1, refraction=variant != "line-of-sight",
+                        magnification=variant not in ("no-magnification", "line-of-sight"))
+    extra = dict(fp32_step=variant == "fp32-step", all_fp32=variant == "all-fp32")
     freqs = corona.log_freqs(3)
-    print("case persistent vs plain", flush=True)
-    a = PU.gpu_trace([m, m], freqs, 45, 3.0, kw, plain=True)
-    b = PU.gpu_trace([m, m], freqs, 45, 3.0, kw, plain=False)
+    print(f"case persistent vs plain {variant}", flush=True)
+    a = PU.gpu_trace([m, m], freqs, 45, 3.0, kw, plain=True, **extra)
+    b = PU.gpu_trace([m, m], freqs, 45, 3.0, kw, plain=False, **extra)
     assert np.array_equal(a["tb"].view(np.uint32), b["tb"].view(np.uint32))
     assert np.array_equal(a["info"].view(np.uint8), b["info"].view(np.uint8))
     assert a["stats"]["ray_steps"] == b["stats"]["ray_steps"]
