@@ -12,7 +12,8 @@ two-stage transfer (Sec. 3.2).  Free-free constants: Dulk (1985).
 
 Parity unpinned (no closed form exists): the oracle on the random-field
 coronae beyond the invariants below.  The ray flags are pinned in
-test_oracle_flags.py.
+test_oracle_flags.py, the record of each ray's discrete decisions in
+test_oracle_events.py and the gradient in test_oracle_grad.py.
 """
 import math
 
