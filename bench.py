@@ -796,6 +796,7 @@ def batching_measure(R, torch, freq_stride=1, refills=(64,)):
     kw = dict(ds_max=wl.ds_max, n_floor=wl.n_floor, max_steps=wl.max_steps)
     res = R.trace_maps(models, freqs, im, R.params(**kw), info=False, stats=True)
     torch.cuda.synchronize()
+    progress("batched: untimed pass done")
     b_ms = timed(lambda: R.trace_maps(models, freqs, im, R.params(**kw), info=False, stats=True, out=res))
     steps = int(R.decode_stats(res["stats"])["ray_steps"])
     progress(f"batched {b_ms:.0f} ms")
