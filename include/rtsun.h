@@ -238,7 +238,8 @@ rt_status rt_autotune(const rt_model* const* models, int32_t n_models, const dou
                       double* best_ms, double* default_ms, void* hip_stream);
 
 /* Trace maps for every (model, frequency) pair.
- *  models[n_models]: all on the current device, sharing one grid kind.
+ *  models[n_models]: all on one device (the call makes it current), sharing
+ *    one grid descriptor; at most 16.  n_freq <= 128.
  *  freq_hz[n_freq]: HOST array, each > 0.
  *  tb_out: DEVICE float32 [n_models][n_freq][nv][nu] (required).
  *  info_out: DEVICE rt_ray_info with the same shape, or NULL.
@@ -299,9 +300,9 @@ rt_status rt_trace_maps_static(const rt_model* const* models, int32_t n_models, 
  * backward from that record.  The image tiles (8 x 8 pixels of one frequency)
  * are traced and swept in batches whose checkpoints (up to 10 KB a ray) fit an
  * 8 GiB budget (the environment variable RT_ADJOINT_CHECKPOINT_BYTES, read at
- * each call, sets another; at least one tile is taken per batch).  Channel adjoints are accumulated per lane and cell in FP32 and
- * added into an FP64 per-vertex accumulator with atomics, so the last bits can
- * vary between runs.  Default precision only: RT_PREC_ALL_FP32, RT_PREC_FP32_STEP,
+ * each call, sets another; at least one tile is taken per batch).  Channel
+ * adjoints are accumulated per lane and cell in FP32 and added into an FP64
+ * per-vertex accumulator with atomics, so the last bits can vary between runs.  Default precision only: RT_PREC_ALL_FP32, RT_PREC_FP32_STEP,
  * RT_DETERMINISTIC_GRAD and RT_TEST_NO_ABSORPTION return RT_E_UNSUPPORTED.  The
  * library keeps a workspace per device and stream (checkpoints, chunk
  * records, accumulator), grown on demand and kept until the process ends; a
